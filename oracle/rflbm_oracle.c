@@ -40,7 +40,8 @@
  *   - the random numbers: Philox4x32-R (Salmon, Moraes, Dror and Shaw, SC'11,
  *     "Parallel random numbers: as easy as 1, 2, 3") with key (seed low word,
  *     seed high word) and counter (node, step, call j = 0..5, stream id); word
- *     w of call j is uniform q = 4j + w, U_q = ((word >> 8) + 1/2) 2^-24; the
+ *     w of call j is uniform q = 4j + w, U_q = ((word >> 8) + 1) 2^-24 in
+ *     (0, 1], a value single precision holds exactly for every word; the
  *     Box-Muller transform of pairs (U_2p, U_2p+1) gives z_2p = R cos(theta),
  *     z_2p+1 = R sin(theta), R = sqrt(-2 ln U_2p), theta = 2 pi U_2p+1; mode k
  *     (4..26) receives r_k = z_(k-4); z_23 is unused.
@@ -233,7 +234,7 @@ void ora_uniforms(uint64_t seed, uint32_t stream_id, uint32_t rounds, uint32_t n
     const uint32_t ctr[4] = {node, step, j, stream_id};
     uint32_t words[4];
     ora_philox4x32(ctr, key, rounds, words);
-    for (int w = 0; w < 4; ++w) u[4 * j + w] = ((double)(words[w] >> 8) + 0.5) / 16777216.0;
+    for (int w = 0; w < 4; ++w) u[4 * j + w] = ((double)(words[w] >> 8) + 1.0) / 16777216.0;
   }
 }
 

@@ -19,9 +19,11 @@ def draw(ora, nodes, step=0, seed=1, stream=0, rounds=10):
 
 def test_uniforms_on_24_bit_grid(ora):
     u = np.concatenate([ora.uniforms(7, 0, 10, n, 3) for n in range(2000)])
-    q = u * 2 ** 24 - 0.5
+    q = u * 2 ** 24 - 1
     np.testing.assert_array_equal(q, np.round(q))
-    assert u.min() > 0 and u.max() < 1
+    assert u.min() > 0 and u.max() <= 1
+    # every value is exact in single precision (24-bit significand)
+    np.testing.assert_array_equal(u.astype(np.float32).astype(np.float64), u)
     assert stats.kstest(u, "uniform").pvalue > 1e-4
 
 
