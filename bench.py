@@ -1,0 +1,204 @@
+"""Throughput of the fused Reg-FLBM D3Q27 step on one MI355X.
+
+Workload (fixed): 512^3 periodic box, rho0 = 1, tau = 0.6 (all hydrodynamic
+modes), ghosts at tau = 1, kT = 1e-5, Philox4x32-10 noise, Taylor-Green initial
+velocity of amplitude 0.01, FP32 population storage.  One step = one fused
+stream + collide kernel over the whole box.  The populations are resident in
+HBM before the timed region starts.
+
+Prints one JSON line: MLUPS (million lattice updates per second), the HBM
+roofline of the step kernel, the CPU oracle baseline on a bounded sample, and
+extra figures (FP16/BF16 storage, deterministic Reg-LBM, copy-kernel ceiling).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS at 512^3 D3Q27 + % HBM roofline; FP16-store vs FP32 at ≤1% "
+          "⟨u²⟩ error")
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_UPDATE = {"f32": 216, "f16": 108, "bf16": 108}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_f32_512_traffic.txt")
+KERNEL_SOURCES = ["paper_2507_08820_amd/csrc/step.hip", "paper_2507_08820_amd/csrc/d3q27.hpp",
+                  "paper_2507_08820_amd/csrc/philox.hpp", "paper_2507_08820_amd/csrc/storage.hpp",
+                  "paper_2507_08820_amd/csrc/kernels.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if it is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0):
+    import torch
+
+    import paper_2507_08820_amd as rf
+    import workloads as wl
+
+    kw = dict(storage=storage, kT=kT, tau=tau, tau_bulk=tau, tau_ghost=1.0, seed=3)
+    lat = rf.Lattice(dims, **kw)
+    rho, u = wl.taylor_green_device(dims, amp=0.01, device=lat.device)
+    lat.init_equilibrium(rho, u)
+    del rho, u
+    lat.stats_config(stats_every)
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = lat.time_steps(steps)  # HIP events on the lattice's stream around the K launches
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.sync()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    n = dims[0] * dims[1] * dims[2]
+    r = dict(ms=ms, wall_s=wall, mlups=n * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps)
+    log(f"{dims} {storage} kT={kT}: {steps} steps, {r['ms_per_step']:.4f} ms/step, "
+        f"{r['mlups']:.0f} MLUPS")
+    return r
+
+
+def copy_ceiling(nbytes=4 << 30, reps=20):
+    import torch
+
+    import paper_2507_08820_amd as rf
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    rf.copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rf.copy(dst, src, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec / 1e9
+
+
+def cpu_baseline(min_seconds=10.0, max_steps=10):
+    """The FP64 oracle as it stands on the host cores, on a 128^3 sample of the
+    same workload (Taylor-Green, tau 0.6, kT 1e-5)."""
+    import oracle
+    import workloads as wl
+
+    dims = (128, 128, 128)
+    rho, u = wl.taylor_green(dims, amp=0.01)
+    f = oracle.init_equilibrium(dims, rho, u)
+    p = oracle.make_params(kT=1e-5, tau_shear=0.6, tau_bulk=0.6, seed=3)
+    n = dims[0] * dims[1] * dims[2]
+    steps, t0 = 0, time.perf_counter()
+    while steps < max_steps and (time.perf_counter() - t0) < min_seconds:
+        f = oracle.step(p, dims, f, steps)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"128^3 Taylor-Green box (same tau, kT, noise), {steps} steps, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the Reg-FLBM path here is single-GPU "
+              "(no multi-GPU sharding is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    dims = (args.size,) * 3
+    main_run = run_gpu(dims, "f32", 1e-5, args.steps, args.warmup)
+    n = dims[0] * dims[1] * dims[2]
+    achieved = BYTES_PER_UPDATE["f32"] * n / (main_run["ms_per_step"] * 1e-3) / 1e9
+    traffic = measured_traffic() if dims == (512, 512, 512) else None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+
+    extra = {}
+    if not args.no_extra:
+        short = max(20, args.steps // 4)
+        for name, storage, kT in (("f16_store", "f16", 1e-5), ("bf16_store", "bf16", 1e-5),
+                                  ("reg_lbm_kT0_f32", "f32", 0.0)):
+            r = run_gpu(dims, storage, kT, short, 5)
+            extra[name] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                           "hbm_gbs": round(BYTES_PER_UPDATE[storage] * n / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
+        extra["f16_gain_over_f32"] = round(extra["f16_store"]["mlups"] / main_run["mlups"], 3)
+        extra["noise_cost_factor"] = round(extra["reg_lbm_kT0_f32"]["mlups"] / main_run["mlups"], 3)
+        cc = copy_ceiling()
+        log(f"copy kernel: {cc:.0f} GB/s")
+        extra["copy_kernel_GBps"] = round(cc, 1)
+        extra["frac_of_copy_ceiling"] = round(achieved / cc, 4)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    if cpu:
+        log(f"cpu oracle: {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Reg-FLBM D3Q27 {dims[0]}^3 periodic box, Taylor-Green A=0.01, "
+                               "rho0=1, tau=0.6, ghost tau=1, kT=1e-5, Philox4x32-10, FP32 storage",
+                   "box": list(dims), "tau": 0.6, "kT": 1e-5, "storage": "f32"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

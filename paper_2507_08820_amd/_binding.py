@@ -1,0 +1,307 @@
+"""ctypes binding of librflbm (include/rflbm.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of librflbm.so.  PyTorch provides
+device memory (the lattice buffer and readback tensors) and the HIP stream.
+If the library has not been built, loading fails with an ImportError instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librflbm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "rflbm.h")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+MODEL = {"reg": 0, "bgk": 1}
+M_RHO, M_J, M_PI = 1, 2, 4
+FIELDS = ("rho", "jx", "jy", "jz", "pi_xx", "pi_yy", "pi_zz", "pi_xy", "pi_xz", "pi_yz")
+
+
+class RFLBMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rflbm status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("model", ctypes.c_int32),
+        ("philox_rounds", ctypes.c_uint32),
+        ("rho0", ctypes.c_double), ("kT", ctypes.c_double),
+        ("tau_shear", ctypes.c_double), ("tau_bulk", ctypes.c_double),
+        ("tau_ghost", ctypes.c_double * 17),
+        ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("storage_scale", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("samples", ctypes.c_int64), ("nodes", ctypes.c_int64),
+        ("sum_drho", ctypes.c_double), ("sum_drho2", ctypes.c_double),
+        ("sum_j", ctypes.c_double * 3), ("sum_j2", ctypes.c_double * 3),
+        ("sum_u2", ctypes.c_double * 3),
+        ("sum_pi", ctypes.c_double * 6), ("sum_pi2", ctypes.c_double * 6),
+        ("mass_dev", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "samples": self.samples, "nodes": self.nodes,
+            "sum_drho": self.sum_drho, "sum_drho2": self.sum_drho2,
+            "sum_j": np.array(self.sum_j[:]), "sum_j2": np.array(self.sum_j2[:]),
+            "sum_u2": np.array(self.sum_u2[:]),
+            "sum_pi": np.array(self.sum_pi[:]), "sum_pi2": np.array(self.sum_pi2[:]),
+            "mass_dev": self.mass_dev, "momentum": np.array(self.momentum[:]),
+        }
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_PP = ctypes.POINTER(Params)
+_SIGS = {
+    "rflbm_params_default": (None, [_PP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "rflbm_required_bytes": (ctypes.c_size_t, [_PP]),
+    "rflbm_create": (ctypes.c_int, [_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "rflbm_destroy": (ctypes.c_int, [_VP]),
+    "rflbm_set_params": (ctypes.c_int, [_VP, _PP]),
+    "rflbm_get_params": (ctypes.c_int, [_VP, _PP]),
+    "rflbm_init_equilibrium": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
+    "rflbm_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
+    "rflbm_sync": (ctypes.c_int, [_VP]),
+    "rflbm_step_count": (ctypes.c_int64, [_VP]),
+    "rflbm_set_step_count": (ctypes.c_int, [_VP, ctypes.c_int64]),
+    "rflbm_get_populations": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
+    "rflbm_set_populations": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
+    "rflbm_get_moments": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, ctypes.c_int]),
+    "rflbm_stats_config": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "rflbm_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(Stats)]),
+    "rflbm_reset_stats": (ctypes.c_int, [_VP]),
+    "rflbm_sk_sample": (ctypes.c_int, [_VP]),
+    "rflbm_sk_nshells": (ctypes.c_int32, [_VP]),
+    "rflbm_get_sk": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int64)]),
+    "rflbm_reset_sk": (ctypes.c_int, [_VP]),
+    "rflbm_time_steps": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    "rflbm_rng_normals": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP,
+                                         _VP]),
+    "rflbm_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
+    "rflbm_last_error": (ctypes.c_char_p, []),
+    "rflbm_version": (ctypes.c_char_p, []),
+}
+
+
+def load_library():
+    """Loads librflbm.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first "
+                          "(python -m paper_2507_08820_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != OK:
+        raise RFLBMError(status, load_library().rflbm_last_error().decode())
+
+
+def make_params(dims, *, storage="f32", model="reg", kT=0.0, tau=1.0, tau_bulk=None,
+                tau_ghost=1.0, rho0=1.0, seed=1, stream_id=0, philox_rounds=10,
+                storage_scale=0.0) -> Params:
+    lib = load_library()
+    p = Params()
+    lib.rflbm_params_default(ctypes.byref(p), *[int(d) for d in dims])
+    p.storage = STORAGE[storage]
+    p.model = MODEL[model]
+    p.philox_rounds = philox_rounds
+    p.rho0 = rho0
+    p.kT = kT
+    p.tau_shear = tau
+    p.tau_bulk = tau if tau_bulk is None else tau_bulk
+    tg = np.broadcast_to(np.asarray(tau_ghost, dtype=np.float64), (17,))
+    for k in range(17):
+        p.tau_ghost[k] = float(tg[k])
+    p.seed = seed
+    p.stream_id = stream_id
+    p.storage_scale = storage_scale
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _as_device_f64(a, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+class Lattice:
+    """A periodic D3Q27 box stepped by the Reg-FLBM kernels of librflbm."""
+
+    def __init__(self, dims, device="cuda", stream=None, **kw):
+        torch = _torch()
+        self.lib = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.n = int(np.prod(self.dims))
+        self.device = torch.device(device)
+        self.params = make_params(self.dims, **kw)
+        nbytes = self.lib.rflbm_required_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            # re-run create to obtain the validation message
+            handle = _VP()
+            check(self.lib.rflbm_create(ctypes.byref(self.params), None, 0, None,
+                                        ctypes.byref(handle)))
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = _dev_ptr(self._buf)
+        self._ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = _VP()
+        check(self.lib.rflbm_create(ctypes.byref(self.params), _VP(self._ptr), nbytes,
+                                    _VP(self.stream.cuda_stream), ctypes.byref(self._h)))
+
+    # -- life cycle --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.rflbm_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- parameters and time ----------------------------------------------
+    @property
+    def t(self) -> int:
+        return int(self.lib.rflbm_step_count(self._h))
+
+    @t.setter
+    def t(self, value: int):
+        check(self.lib.rflbm_set_step_count(self._h, int(value)))
+
+    def set_params(self, **kw):
+        p = make_params(self.dims, **kw)
+        check(self.lib.rflbm_set_params(self._h, ctypes.byref(p)))
+        self.params = p
+
+    # -- state ---------------------------------------------------------------
+    def init_equilibrium(self, rho=None, u=None):
+        r = None if rho is None else _as_device_f64(np.broadcast_to(rho, (self.n,))
+                                                     if not hasattr(rho, "data_ptr") else rho,
+                                                     self.device)
+        v = None if u is None else _as_device_f64(u, self.device).reshape(3, self.n)
+        check(self.lib.rflbm_init_equilibrium(self._h, None if r is None else _VP(_dev_ptr(r)),
+                                              None if v is None else _VP(_dev_ptr(v)), 0))
+        self._keep = (r, v)  # alive until the stream has consumed them
+        self.stream.synchronize()
+
+    def populations(self):
+        """f(x, t) as a (27, N) float64 tensor on the device."""
+        torch = _torch()
+        out = torch.empty((27, self.n), dtype=torch.float64, device=self.device)
+        check(self.lib.rflbm_get_populations(self._h, _VP(_dev_ptr(out)), 0))
+        return out
+
+    def set_populations(self, f):
+        d = _as_device_f64(f, self.device).reshape(27, self.n)
+        check(self.lib.rflbm_set_populations(self._h, _VP(_dev_ptr(d)), 0))
+        self.stream.synchronize()
+
+    def moments(self, mask=M_RHO | M_J | M_PI):
+        torch = _torch()
+        nf = (1 if mask & M_RHO else 0) + (3 if mask & M_J else 0) + (6 if mask & M_PI else 0)
+        out = torch.empty((nf, self.n), dtype=torch.float32, device=self.device)
+        check(self.lib.rflbm_get_moments(self._h, mask, _VP(_dev_ptr(out)), 0))
+        return out
+
+    # -- stepping --------------------------------------------------------------
+    def step(self, nsteps=1):
+        check(self.lib.rflbm_step(self._h, int(nsteps)))
+
+    def sync(self):
+        check(self.lib.rflbm_sync(self._h))
+
+    def time_steps(self, nsteps) -> float:
+        ms = ctypes.c_double()
+        check(self.lib.rflbm_time_steps(self._h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
+
+    # -- observables -----------------------------------------------------------
+    def stats_config(self, every):
+        check(self.lib.rflbm_stats_config(self._h, int(every)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        check(self.lib.rflbm_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        check(self.lib.rflbm_reset_stats(self._h))
+
+    def sk_sample(self):
+        check(self.lib.rflbm_sk_sample(self._h))
+
+    def sk(self, field):
+        ns = self.lib.rflbm_sk_nshells(self._h)
+        sums = np.zeros(ns)
+        counts = np.zeros(ns, dtype=np.int64)
+        samples = ctypes.c_int64()
+        idx = FIELDS.index(field) if isinstance(field, str) else int(field)
+        check(self.lib.rflbm_get_sk(self._h, idx, sums.ctypes.data_as(_VP), counts.ctypes.data_as(_VP),
+                                    ns, ctypes.byref(samples)))
+        return sums, counts, samples.value
+
+    def reset_sk(self):
+        check(self.lib.rflbm_reset_sk(self._h))
+
+
+def rng_normals(seed, stream_id, rounds, node0, count, t, device="cuda"):
+    """The uniforms and normals the step kernel draws (each (count, 24) float32)."""
+    torch = _torch()
+    lib = load_library()
+    u = torch.empty((count, 24), dtype=torch.float32, device=device)
+    z = torch.empty((count, 24), dtype=torch.float32, device=device)
+    s = torch.cuda.current_stream(device)
+    check(lib.rflbm_rng_normals(seed, stream_id, rounds, node0, count, t, _VP(_dev_ptr(u)),
+                                _VP(_dev_ptr(z)), _VP(s.cuda_stream)))
+    s.synchronize()
+    return u, z
+
+
+def copy(dst, src, nbytes, stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(dst.device)
+    check(load_library().rflbm_copy(_VP(_dev_ptr(dst)), _VP(_dev_ptr(src)), int(nbytes),
+                                    _VP(s.cuda_stream)))

@@ -1,0 +1,275 @@
+// aux.hip -- kernels around the step: population readback and write-back in the
+// canonical FP64 layout, equilibrium initialisation (Eq. hermite_feq2 in its
+// product form), moment fields rho, j, Pi (Eqs. eq:rho, eq:u and the Pi of
+// Sec. III), re-encoding of stored deviations, the noise generator exposed for
+// testing, and a plain copy kernel (bandwidth reference).
+//
+// All of these work on the AA layout described in kernels.hpp: at an even step
+// count f_i(x) sits in plane i at x, at an odd one in plane 26 - i at x - c_i.
+#include <hip/hip_runtime.h>
+
+#include "d3q27.hpp"
+#include "kernels.hpp"
+#include "philox.hpp"
+#include "storage.hpp"
+
+namespace rflbm {
+
+namespace {
+
+struct NodeXYZ {
+  uint32_t x, y, z;
+};
+
+__device__ __forceinline__ NodeXYZ coords(uint64_t n, uint32_t nx, uint32_t ny) {
+  NodeXYZ c;
+  c.x = static_cast<uint32_t>(n % nx);
+  const uint64_t r = n / nx;
+  c.y = static_cast<uint32_t>(r % ny);
+  c.z = static_cast<uint32_t>(r / ny);
+  return c;
+}
+
+// Element index of the slot holding f_i(x) at the given parity.
+__device__ __forceinline__ uint64_t slot_index(int i, NodeXYZ p, const GatherArgs& g) {
+  if (!g.odd) return static_cast<uint64_t>(i) * g.pitch + p.x + g.nx * (p.y + static_cast<uint64_t>(g.ny) * p.z);
+  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+  const uint32_t x = wrap_add(p.x, -cx, g.nx), y = wrap_add(p.y, -cy, g.ny), z = wrap_add(p.z, -cz, g.nz);
+  return static_cast<uint64_t>(kQ - 1 - i) * g.pitch + x + g.nx * (y + static_cast<uint64_t>(g.ny) * z);
+}
+
+template <int S>
+__global__ void get_pop_kernel(const GatherArgs g, double* dst) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  const T* pop = static_cast<const T*>(g.pop);
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int cls = speed_class(i);
+      const float d = C::decode(pop[slot_index(i, p, g)], g.sigma[cls]);
+      dst[i * N + n] = class_weight(cls) * g.rho0 + static_cast<double>(d);
+    }
+  }
+}
+
+template <int S>
+__global__ void set_pop_kernel(const GatherArgs g, const double* src) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  T* pop = static_cast<T*>(const_cast<void*>(g.pop));
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int cls = speed_class(i);
+      const double d = src[i * N + n] - class_weight(cls) * g.rho0;
+      pop[slot_index(i, p, g)] = C::encode(static_cast<float>(d), g.inv_sigma[cls]);
+    }
+  }
+}
+
+// f^(0)_i = rho prod_a omega(c_a) [1 + c_a u_a / cs2 + (c_a^2 - cs2) u_a^2 / (2 cs2^2)],
+// the product form of the full-Hermite equilibrium (every Table II mode is a
+// product of 1-D Hermite polynomials, so its Hermite sum factorises by axis).
+template <int S>
+__global__ void init_eq_kernel(const GatherArgs g, const double* rho, const double* u) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  T* pop = static_cast<T*>(const_cast<void*>(g.pop));
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+    const double r = rho ? rho[n] : g.rho0;
+    const double ua[3] = {u ? u[n] : 0.0, u ? u[N + n] : 0.0, u ? u[2 * N + n] : 0.0};
+    double fac[3][3];  // fac[a][c + 1]
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double q = 4.5 * ua[a] * ua[a];
+      fac[a][0] = (1.0 / 6.0) * (1.0 - 3.0 * ua[a] + q - 1.5 * ua[a] * ua[a]);
+      fac[a][1] = (2.0 / 3.0) * (1.0 - 1.5 * ua[a] * ua[a]);
+      fac[a][2] = (1.0 / 6.0) * (1.0 + 3.0 * ua[a] + q - 1.5 * ua[a] * ua[a]);
+    }
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int cls = speed_class(i);
+      const double feq = r * fac[0][i % 3] * fac[1][(i / 3) % 3] * fac[2][i / 9];
+      const double d = feq - class_weight(cls) * g.rho0;
+      pop[slot_index(i, p, g)] = C::encode(static_cast<float>(d), g.inv_sigma[cls]);
+    }
+  }
+}
+
+template <int S>
+__global__ void moments_kernel(const GatherArgs g, uint32_t mask, float* dst) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  const T* pop = static_cast<const T*>(g.pop);
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+    float v[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) v[i] = C::decode(pop[slot_index(i, p, g)], g.sigma[speed_class(i)]);
+    forward27(v);
+    float* out = dst;
+    if (mask & 1u) {
+      out[n] = static_cast<float>(g.rho0 + static_cast<double>(v[0]));
+      out += N;
+    }
+    if (mask & 2u) {
+      out[n] = v[1];
+      out[N + n] = v[3];
+      out[2 * N + n] = v[9];
+      out += 3 * N;
+    }
+    if (mask & 4u) {
+      const int slots[6] = {mode_slot(4), mode_slot(5), mode_slot(6), mode_slot(7), mode_slot(8), mode_slot(9)};
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[c * N + n] = v[slots[c]];
+    }
+  }
+}
+
+// Plane p holds populations of one speed class in either layout (26 - i and i
+// have the same |c|^2), so re-encoding works plane by plane.
+template <int S>
+__global__ void reencode_kernel(const GatherArgs from, const GatherArgs to) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const uint64_t N = static_cast<uint64_t>(from.nx) * from.ny * from.nz;
+  T* pop = static_cast<T*>(const_cast<void*>(from.pop));
+  const uint64_t total = N * kQ;
+  for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < total;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const int plane = static_cast<int>(e / N);
+    const uint64_t n = e - static_cast<uint64_t>(plane) * N;
+    const int cls = speed_class(plane);
+    T* q = pop + static_cast<uint64_t>(plane) * from.pitch + n;
+    const double d = static_cast<double>(C::decode(*q, from.sigma[cls])) +
+                     class_weight(cls) * (from.rho0 - to.rho0);
+    *q = C::encode(static_cast<float>(d), to.inv_sigma[cls]);
+  }
+}
+
+template <int R>
+__global__ void rng_kernel(uint32_t key0, uint32_t key1, uint32_t sid, uint32_t node0, uint32_t count,
+                           uint32_t step, float* u, float* z) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const uint32_t node = node0 + t;
+#pragma unroll
+  for (uint32_t j = 0; j < 6; ++j) {
+    const Word4 w = philox<R>(Word4{node, step, j, sid}, key0, key1);
+    const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+    float r[4];
+    box_muller(w.w0, w.w1, r[0], r[1]);
+    box_muller(w.w2, w.w3, r[2], r[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      u[static_cast<uint64_t>(t) * 24 + 4 * j + q] = word_to_uniform(ws[q]);
+      z[static_cast<uint64_t>(t) * 24 + 4 * j + q] = r[q];
+    }
+  }
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void copy_kernel(u32x4* __restrict__ dst, const u32x4* __restrict__ src, uint64_t n) {
+  for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    __builtin_nontemporal_store(src[e], dst + e);
+}
+
+__global__ void fill_zero_kernel(double* dst, uint64_t n) {
+  for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    dst[e] = 0.0;
+}
+
+uint32_t grid_for(uint64_t work, uint32_t block) {
+  const uint64_t g = (work + block - 1) / block;
+  return static_cast<uint32_t>(g < 65536 ? (g == 0 ? 1 : g) : 65536);
+}
+
+}  // namespace
+
+#define RFLBM_DISPATCH_STORAGE(storage, KERNEL, grid, block, stream, ...)                  \
+  do {                                                                                      \
+    switch (storage) {                                                                      \
+      case kF32: hipLaunchKernelGGL(KERNEL<kF32>, grid, block, 0, stream, __VA_ARGS__); break;   \
+      case kF16: hipLaunchKernelGGL(KERNEL<kF16>, grid, block, 0, stream, __VA_ARGS__); break;   \
+      case kBF16: hipLaunchKernelGGL(KERNEL<kBF16>, grid, block, 0, stream, __VA_ARGS__); break; \
+      default: return hipErrorInvalidValue;                                                 \
+    }                                                                                       \
+  } while (0)
+
+hipError_t launch_get_populations(int storage, const GatherArgs& g, double* dst, hipStream_t s) {
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  RFLBM_DISPATCH_STORAGE(storage, get_pop_kernel, dim3(grid_for(N, 256)), dim3(256), s, g, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_populations(int storage, const GatherArgs& g, const double* src, hipStream_t s) {
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  RFLBM_DISPATCH_STORAGE(storage, set_pop_kernel, dim3(grid_for(N, 256)), dim3(256), s, g, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_equilibrium(int storage, const GatherArgs& g, const double* rho,
+                                   const double* u, hipStream_t s) {
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  RFLBM_DISPATCH_STORAGE(storage, init_eq_kernel, dim3(grid_for(N, 256)), dim3(256), s, g, rho, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_moments(int storage, const GatherArgs& g, uint32_t mask, float* dst,
+                              hipStream_t s) {
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  RFLBM_DISPATCH_STORAGE(storage, moments_kernel, dim3(grid_for(N, 256)), dim3(256), s, g, mask, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_reencode(int storage, const GatherArgs& from, const GatherArgs& to, hipStream_t s) {
+  const uint64_t N = static_cast<uint64_t>(from.nx) * from.ny * from.nz;
+  RFLBM_DISPATCH_STORAGE(storage, reencode_kernel, dim3(grid_for(N * kQ, 256)), dim3(256), s, from, to);
+  return hipGetLastError();
+}
+
+hipError_t launch_rng_normals(uint32_t key0, uint32_t key1, uint32_t stream_id, int rounds,
+                              uint32_t node0, uint32_t count, uint32_t step, float* u, float* z,
+                              hipStream_t s) {
+  const dim3 grid((count + 255) / 256), block(256);
+  if (count == 0) return hipSuccess;
+  if (rounds == 10)
+    hipLaunchKernelGGL(rng_kernel<10>, grid, block, 0, s, key0, key1, stream_id, node0, count, step, u, z);
+  else if (rounds == 7)
+    hipLaunchKernelGGL(rng_kernel<7>, grid, block, 0, s, key0, key1, stream_id, node0, count, step, u, z);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const uint64_t n = bytes / sizeof(u32x4);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256) < 8192 ? grid_for(n, 256) : 8192), dim3(256),
+                     0, s, static_cast<u32x4*>(dst), static_cast<const u32x4*>(src), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst,
+                     static_cast<uint64_t>(n));
+  return hipGetLastError();
+}
+
+}  // namespace rflbm

@@ -1,0 +1,99 @@
+// kernels.hpp -- internal interface between the C-ABI layer (api.cpp) and the HIP
+// kernels of the fluctuating lattice Boltzmann step (arXiv:2507.08820, Sec. II).
+//
+// Population storage ("AA" in-place streaming, one lattice copy): 27 planes
+// A[i][n] of `pitch` elements each, n = x + nx (y + ny z), holding the deviation
+// f - w_i rho0 (divided by sigma_class(i) for 16-bit storage).
+//   After an even number t of steps: f_i(x, t) = A[i][x].
+//   After an odd number t of steps:  f_i(x, t) = A[26 - i][x - c_i].
+// An even step reads A[i][x] and writes f*_i(x) to A[26 - i][x]; an odd step
+// reads A[26 - i][x - c_i] and writes f*_i(x) to A[i][x + c_i].  In both cases
+// every slot is read and then written by the same thread, so the update is
+// race free in place, and the stored state after the step is the streamed
+// f(t + 1) of Eq. eq:streaming.
+#pragma once
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace rflbm {
+
+enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+constexpr int kNumStats = 23;  // per-node statistics accumulated by the step kernel
+// column layout: 0 drho, 1 drho^2, 2-4 j, 5-7 j^2, 8-10 u^2, 11-16 Pi, 17-22 Pi^2
+constexpr int kAccDoubles = 32;  // device accumulator block: 23 sums, samples, mass, momentum
+
+struct StepArgs {
+  void* pop;             // population planes
+  uint64_t pitch;        // elements per plane
+  uint32_t nx, ny, nz;   // box
+  uint32_t tiles_x;      // tiles along x (tile = blockDim.x x blockDim.y nodes of one z plane)
+  uint32_t tiles_y;      // tiles along y
+  uint32_t ntiles;       // tiles_x * tiles_y * nz
+  uint32_t xcd_remap;    // 1: give each XCD a contiguous range of tiles
+  uint32_t step;         // t mod 2^32 (Philox counter word 1)
+  uint32_t key0, key1;   // Philox key
+  uint32_t stream_id;    // Philox counter word 3
+  float rho0;
+  float lam_s;           // 1 - omega_s (deviatoric second-order modes)
+  float lam_b_minus_s;   // (1 - omega_b) - (1 - omega_s) (trace of the xx, yy, zz block)
+  float amp_s;           // sqrt(kT b_4 / cs2) s(omega_s), s(w) = sqrt(w (2 - w)); modes 4..6
+  float amp_b_minus_s;   // sqrt(kT b_4 / cs2) (s(omega_b) - s(omega_s))
+  float amp_off;         // sqrt(kT b_7 / cs2) s(omega_s), modes 7..9
+  float lam_g[17];       // 1 - omega_g,k, k = 10..26
+  float amp_g[17];       // sqrt(kT b_k / cs2) s(omega_g,k)
+  float sigma[4];        // storage unit per speed class (1 for FP32)
+  float inv_sigma[4];
+  int* flag;             // set to 1 on rho <= 0 or non-finite rho, j
+  double* partials;      // statistics partials, column-major [kNumStats][gridDim.x]
+};
+
+// Launch configuration of the step kernel.
+struct Launch {
+  uint32_t bx, by;   // block shape (bx * by <= 256, bx multiple of 64)
+  uint32_t grid;     // number of blocks (ntiles rounded up to a multiple of 8)
+};
+
+Launch make_launch(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t bx, uint32_t by);
+
+// One fused stream + collide step on `stream`.  rounds: 0 (no noise), 7 or 10.
+hipError_t launch_step(int storage, bool odd, int rounds, bool stats, const StepArgs& a,
+                       const Launch& l, hipStream_t stream);
+
+// Deterministic reduction of the statistics partials into the accumulators.
+// scratch holds at least 2 * kNumStats * ceil(grid / 2048) doubles.
+hipError_t launch_stats_reduce(const double* partials, uint32_t grid, double* scratch,
+                               double* acc, hipStream_t stream);
+
+struct GatherArgs {
+  const void* pop;
+  uint64_t pitch;
+  uint32_t nx, ny, nz;
+  uint32_t odd;           // parity of the current step count
+  double rho0;
+  float sigma[4];
+  float inv_sigma[4];
+};
+
+// f(x, t) -> dst[i * N + n] (FP64, absolute populations).
+hipError_t launch_get_populations(int storage, const GatherArgs& g, double* dst, hipStream_t s);
+// src[i * N + n] (FP64, absolute) -> storage slots for step parity g.odd.
+hipError_t launch_set_populations(int storage, const GatherArgs& g, const double* src,
+                                  hipStream_t s);
+// Equilibrium f^(0)(rho, u) (rho, u may be null) -> storage slots.
+hipError_t launch_init_equilibrium(int storage, const GatherArgs& g, const double* rho,
+                                   const double* u, hipStream_t s);
+// Moment fields (FP32, planar) selected by mask (1 rho, 2 j, 4 Pi).
+hipError_t launch_get_moments(int storage, const GatherArgs& g, uint32_t mask, float* dst,
+                              hipStream_t s);
+// Re-encodes stored deviations after a change of rho0 or sigma.
+hipError_t launch_reencode(int storage, const GatherArgs& from, const GatherArgs& to,
+                           hipStream_t s);
+
+hipError_t launch_rng_normals(uint32_t key0, uint32_t key1, uint32_t stream_id, int rounds,
+                              uint32_t node0, uint32_t count, uint32_t step, float* u, float* z,
+                              hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_fill_zero(double* dst, size_t n, hipStream_t s);
+
+}  // namespace rflbm

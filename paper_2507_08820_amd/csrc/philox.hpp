@@ -1,0 +1,68 @@
+// philox.hpp -- counter-based normal random numbers for the noise term of the
+// fluctuating update (arXiv:2507.08820, Eq. fluct_phi: r_k ~ N(0, 1); the paper
+// does not name its generator).
+//
+// Generator: Philox4x32 of Salmon, Moraes, Dror and Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3" (SC'11).  One round takes the 128-bit counter as
+// four 32-bit words, forms the 64-bit products of words 0 and 2 with two fixed
+// odd multipliers, and returns (hi(product 2) ^ word 1 ^ key 0,
+// lo(product 2), hi(product 0) ^ word 3 ^ key 1, lo(product 0)); the two key
+// words advance by Weyl increments between rounds.
+//
+// Use in the step kernel: key = (seed low, seed high), counter =
+// (node, step, call j, stream id), j = 0..5.  Each 32-bit word w gives a
+// uniform U = ((w >> 8) + 1) 2^-24 in (0, 1], exact in FP32.  Words (0, 1) and
+// (2, 3) of a call are Box-Muller pairs: R = sqrt(-2 ln U0), z0 = R cos(2 pi U1),
+// z1 = R sin(2 pi U1).  On gfx950 the hardware sine and cosine take their
+// argument in revolutions, so 2 pi U needs no range reduction, and the hardware
+// logarithm is base 2, so ln U0 = ln 2 log2 U0.
+#pragma once
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace rflbm {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;  // multiplier of word 0
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;  // multiplier of word 2
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;  // key-0 increment (golden ratio)
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;  // key-1 increment (sqrt(3) - 1)
+
+struct Word4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+// R rounds of Philox4x32 on counter c with key (k0, k1).
+template <int R>
+__host__ __device__ __forceinline__ Word4 philox(Word4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * c.w0;
+    const uint64_t p2 = static_cast<uint64_t>(kPhiloxM1) * c.w2;
+    Word4 n;
+    n.w0 = static_cast<uint32_t>(p2 >> 32) ^ c.w1 ^ k0;
+    n.w1 = static_cast<uint32_t>(p2);
+    n.w2 = static_cast<uint32_t>(p0 >> 32) ^ c.w3 ^ k1;
+    n.w3 = static_cast<uint32_t>(p0);
+    c = n;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  return c;
+}
+
+// Uniform in (0, 1] from the top 24 bits of a word; exact in FP32.
+__device__ __forceinline__ float word_to_uniform(uint32_t w) {
+  return fmaf(static_cast<float>(w >> 8), 0x1p-24f, 0x1p-24f);
+}
+
+// Box-Muller pair from two words (radius word, angle word).
+__device__ __forceinline__ void box_muller(uint32_t wr, uint32_t wa, float& z0, float& z1) {
+  const float ur = word_to_uniform(wr);
+  const float ua = word_to_uniform(wa);
+  constexpr float kMinus2Ln2 = -1.38629436111989061883f;  // -2 ln 2
+  const float rad = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(ur));
+  z0 = rad * __builtin_amdgcn_cosf(ua);
+  z1 = rad * __builtin_amdgcn_sinf(ua);
+}
+
+}  // namespace rflbm

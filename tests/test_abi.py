@@ -1,0 +1,100 @@
+"""CPU checks of the C interface: the library loads, exports every function the
+header declares, the ctypes structures match the C layout, and parameter
+validation rejects what the model forbids (tau <= 1/2 makes the noise
+amplitude of Eq. fluct_phi imaginary).  No GPU work is launched here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2507_08820_amd as rf
+from paper_2507_08820_amd import _binding
+
+HEADER = _binding.HEADER
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rflbm_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = rf.load_library()
+    names = declared_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert set(names) == set(_binding._SIGS)
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(f"""
+#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rflbm_params), offsetof(rflbm_params, rho0),
+         offsetof(rflbm_params, tau_ghost), offsetof(rflbm_params, seed),
+         offsetof(rflbm_params, storage_scale), sizeof(rflbm_stats), offsetof(rflbm_stats, mass_dev));
+  return 0;
+}}
+""")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    P, S = _binding.Params, _binding.Stats
+    assert got == [ctypes.sizeof(P), P.rho0.offset, P.tau_ghost.offset, P.seed.offset,
+                   P.storage_scale.offset, ctypes.sizeof(S), S.mass_dev.offset]
+
+
+def required(dims, **kw):
+    p = rf.make_params(dims, **kw)
+    return rf.load_library().rflbm_required_bytes(ctypes.byref(p))
+
+
+def test_required_bytes_counts_one_lattice_copy():
+    n = 512 ** 3
+    b = required((512, 512, 512))
+    assert 27 * 4 * n <= b < 27 * 4 * n * 1.02
+    b16 = required((512, 512, 512), storage="f16", kT=1e-5)
+    assert 27 * 2 * n <= b16 < 27 * 2 * n * 1.02
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tau=0.5), dict(tau=0.4), dict(tau_bulk=0.5), dict(tau_ghost=0.5), dict(kT=-1.0),
+    dict(rho0=0.0), dict(philox_rounds=8), dict(storage="f16", kT=0.0),
+])
+def test_invalid_parameters_are_rejected(kw):
+    assert required((8, 8, 8), **kw) == 0
+    p = rf.make_params((8, 8, 8), **kw)
+    h = ctypes.c_void_p()
+    lib = rf.load_library()
+    assert lib.rflbm_create(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == _binding.EINVAL
+    assert lib.rflbm_last_error()
+
+
+@pytest.mark.parametrize("dims", [(1, 8, 8), (8, 8, 1), (2048, 2048, 1024), (1100, 1000, 1000)])
+def test_invalid_boxes_are_rejected(dims):
+    assert required(dims) == 0
+
+
+def test_caller_buffer_too_small_is_enomem():
+    p = rf.make_params((8, 8, 8))
+    h = ctypes.c_void_p()
+    lib = rf.load_library()
+    need = lib.rflbm_required_bytes(ctypes.byref(p))
+    st = lib.rflbm_create(ctypes.byref(p), ctypes.c_void_p(1 << 20), need - 1, None, ctypes.byref(h))
+    assert st == _binding.ENOMEM and not h.value
+
+
+def test_null_arguments():
+    lib = rf.load_library()
+    assert lib.rflbm_step(None, 1) == _binding.EINVAL
+    assert lib.rflbm_step_count(None) == -1
+    assert lib.rflbm_destroy(None) == _binding.OK

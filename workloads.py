@@ -46,11 +46,34 @@ def taylor_green(dims, amp=0.01, rho0=1.0):
     u_z = 0,  k_a = 2 pi / n_a.
     """
     nx, ny, nz = dims
-    x, y, z = grid(dims)
-    kx, ky, kz = 2 * np.pi / nx, 2 * np.pi / ny, 2 * np.pi / nz
+    sx, cx = np.sin(2 * np.pi * np.arange(nx) / nx), np.cos(2 * np.pi * np.arange(nx) / nx)
+    sy, cy = np.sin(2 * np.pi * np.arange(ny) / ny), np.cos(2 * np.pi * np.arange(ny) / ny)
+    cz = np.cos(2 * np.pi * np.arange(nz) / nz)
     rho, u = rest(dims, rho0)
-    u[0] = amp * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)
-    u[1] = -amp * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)
+    u[0] = (amp * sx[None, None, :] * cy[None, :, None] * cz[:, None, None]).ravel()
+    u[1] = (-amp * cx[None, None, :] * sy[None, :, None] * cz[:, None, None]).ravel()
+    return rho, u
+
+
+def taylor_green_device(dims, amp=0.01, rho0=1.0, device="cuda"):
+    """taylor_green built in device memory with torch (for large boxes).
+
+    The same 1-D factors are multiplied in the same order in FP64, so the
+    values equal those of taylor_green.  Returns (rho, u) torch tensors of
+    shapes (N,) and (3, N).
+    """
+    import torch
+
+    nx, ny, nz = dims
+    f = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device)
+    sx, cx = f(np.sin(2 * np.pi * np.arange(nx) / nx)), f(np.cos(2 * np.pi * np.arange(nx) / nx))
+    sy, cy = f(np.sin(2 * np.pi * np.arange(ny) / ny)), f(np.cos(2 * np.pi * np.arange(ny) / ny))
+    cz = f(np.cos(2 * np.pi * np.arange(nz) / nz))
+    n = nx * ny * nz
+    u = torch.zeros((3, n), dtype=torch.float64, device=device)
+    u[0] = (amp * sx[None, None, :] * cy[None, :, None] * cz[:, None, None]).reshape(n)
+    u[1] = (-amp * cx[None, None, :] * sy[None, :, None] * cz[:, None, None]).reshape(n)
+    rho = torch.full((n,), float(rho0), dtype=torch.float64, device=device)
     return rho, u
 
 
