@@ -27,9 +27,10 @@ METRIC = ("MLUPS at 512^3 D3Q27 + % HBM roofline; FP16-store vs FP32 at ≤1% "
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_UPDATE = {"f32": 216, "f16": 108, "bf16": 108}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_f32_512_traffic.txt")
-KERNEL_SOURCES = ["paper_2507_08820_amd/csrc/step.hip", "paper_2507_08820_amd/csrc/d3q27.hpp",
-                  "paper_2507_08820_amd/csrc/philox.hpp", "paper_2507_08820_amd/csrc/storage.hpp",
-                  "paper_2507_08820_amd/csrc/kernels.hpp"]
+KERNEL_SOURCES = ["paper_2507_08820_amd/csrc/step.hip", "paper_2507_08820_amd/csrc/node_body.inc",
+                  "paper_2507_08820_amd/csrc/d3q27.hpp", "paper_2507_08820_amd/csrc/philox.hpp",
+                  "paper_2507_08820_amd/csrc/storage.hpp", "paper_2507_08820_amd/csrc/kernels.hpp",
+                  "paper_2507_08820_amd/csrc/fastdiv.hpp"]
 
 
 def kernel_hash() -> str:
@@ -93,6 +94,64 @@ def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0):
     return r
 
 
+def run_batch(storage, steps=200, graph_steps=20):
+    """The 64-replica workload: boxes 32^3..96^3, tau in [0.55, 1.2], kT in
+    [1e-6, 1e-4], Taylor-Green A = 0.01 per box; aggregate MLUPS of the
+    persistent hipGraph-replayed launch and of one launch per replica."""
+    import torch
+
+    import paper_2507_08820_amd as rf
+    import workloads as wl
+
+    table = wl.replica_table(64, seed=5)
+    reps = [dict(dims=t["dims"], kT=t["kT"], tau=t["tau"], seed=t["seed"], stream_id=t["stream_id"])
+            for t in table]
+    b = rf.Batch(reps, storage=storage)
+    for r, t in enumerate(table):
+        rho, u = wl.taylor_green_device(t["dims"], amp=0.01, device=b.device)
+        b[r].init_equilibrium(rho, u)
+    b.set_launch(256, 8, graph_steps)
+    tile, bpc, _ = b.autotune(trial_steps=10)
+    b.set_launch(tile, bpc, graph_steps)
+    b.step(graph_steps)
+    b.sync()
+    ms = b.time_steps(steps)
+    b.sync()
+    sep_steps = max(10, steps // 10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step_separate(sep_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_sep = e0.elapsed_time(e1)
+    b.sync()
+    n = b.nodes
+    out = {"replicas": len(reps), "nodes": n, "tile": tile, "blocks_per_cu": bpc,
+           "graph_steps": graph_steps,
+           "mlups_persistent_graph": round(n * steps / (ms * 1e-3) / 1e6, 1),
+           "mlups_one_launch_per_replica": round(n * sep_steps / (ms_sep * 1e-3) / 1e6, 1)}
+    out["gain"] = round(out["mlups_persistent_graph"] / out["mlups_one_launch_per_replica"], 3)
+    log(f"batch {storage}: {out}")
+    b.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def profile_run(dims):
+    import torch
+
+    import paper_2507_08820_amd as rf
+
+    run_gpu(dims, "f32", 1e-5, 4, 2)
+    nbytes = 1 << 30
+    src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    rf.copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    log(f"copied {nbytes} bytes")
+
+
 def copy_ceiling(nbytes=4 << 30, reps=20):
     import torch
 
@@ -144,6 +203,9 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: 2 warm-up and 4 timed steps of the bench "
+                         "workload, then one copy of 1 GiB (the counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Reg-FLBM path here is single-GPU "
@@ -151,6 +213,9 @@ def main():
         sys.exit(2)
 
     dims = (args.size,) * 3
+    if args.profile:
+        profile_run(dims)
+        return
     main_run = run_gpu(dims, "f32", 1e-5, args.steps, args.warmup)
     n = dims[0] * dims[1] * dims[2]
     achieved = BYTES_PER_UPDATE["f32"] * n / (main_run["ms_per_step"] * 1e-3) / 1e9
@@ -168,6 +233,8 @@ def main():
                            "hbm_gbs": round(BYTES_PER_UPDATE[storage] * n / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
         extra["f16_gain_over_f32"] = round(extra["f16_store"]["mlups"] / main_run["mlups"], 3)
         extra["noise_cost_factor"] = round(extra["reg_lbm_kT0_f32"]["mlups"] / main_run["mlups"], 3)
+        extra["batch64_f32"] = run_batch("f32")
+        extra["batch64_f16"] = run_batch("f16")
         cc = copy_ceiling()
         log(f"copy kernel: {cc:.0f} GB/s")
         extra["copy_kernel_GBps"] = round(cc, 1)

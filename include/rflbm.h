@@ -202,9 +202,76 @@ rflbm_status rflbm_get_sk(rflbm_lattice* lat, int32_t field, double* shell_sum,
                           int64_t* shell_count, int32_t nshells, int64_t* samples);
 rflbm_status rflbm_reset_sk(rflbm_lattice* lat);
 
+/* Launch shape of the step kernel: blocks of bx x (256 / bx) nodes of one
+ * z plane, bx in {64, 128, 256}; xcd_remap != 0 hands each of the 8 XCDs a
+ * contiguous range of tiles (neighbouring tiles then share an L2).  Any shape
+ * gives the same results bit for bit.  rflbm_create picks the widest bx that
+ * the box's x extent fills. */
+rflbm_status rflbm_set_launch(rflbm_lattice* lat, int32_t bx, int32_t xcd_remap);
+rflbm_status rflbm_get_launch(const rflbm_lattice* lat, int32_t* bx, int32_t* xcd_remap);
+
 /* Times nsteps steps with HIP events recorded on the lattice's own stream and
  * waits for them; *ms gets the elapsed milliseconds.  Used by benchmarks. */
 rflbm_status rflbm_time_steps(rflbm_lattice* lat, int64_t nsteps, double* ms);
+
+/* ------------------------------------------------------------------------
+ * Batched replicas.  Fluctuation statistics need many independent noise
+ * realisations; a batch holds n boxes (each with its own size, taus, k_BT,
+ * rho0, seed and stream id, one common storage type and Philox round count) in
+ * one buffer and advances all of them by one persistent kernel launch per step
+ * (Eq. r-flbe2 at every node of every replica).  Replica r evolves exactly as a
+ * stand-alone lattice with params p[r] would, bit for bit.
+ * Every replica shares the batch's step count t. */
+typedef struct rflbm_batch rflbm_batch;
+
+/* Device bytes for n replicas with params p[0..n-1], 0 if invalid. */
+size_t rflbm_batch_required_bytes(int32_t n, const rflbm_params* p);
+/* Creates a batch (buffer ownership and stream as for rflbm_create); every
+ * replica starts at rest, t = 0.  EINVAL if any params are invalid or if the
+ * replicas differ in storage type or Philox rounds. */
+rflbm_status rflbm_batch_create(int32_t n, const rflbm_params* p, void* dev_buf, size_t bytes,
+                                void* hip_stream, rflbm_batch** out);
+/* Waits for the stream and releases the batch and its replica views. */
+rflbm_status rflbm_batch_destroy(rflbm_batch* b);
+/* Borrowed view of replica r: every rflbm_* lattice call that reads or writes
+ * state works on it (populations, moments, S(k), init, set_populations,
+ * statistics configuration); stepping, re-timing and parameter changes go
+ * through the batch (the lattice calls return ESTATE on a view).  The view
+ * lives as long as the batch; rflbm_destroy on it returns ESTATE. */
+rflbm_status rflbm_batch_lattice(rflbm_batch* b, int32_t r, rflbm_lattice** view);
+/* Replaces the parameters of replica r (same rules as rflbm_set_params). */
+rflbm_status rflbm_batch_set_params(rflbm_batch* b, int32_t r, const rflbm_params* p);
+/* Advances every replica nsteps steps: one persistent launch per step, or
+ * replays of a captured graph of graph_steps steps (rflbm_batch_set_launch)
+ * whenever t is even.  Asynchronous on the batch stream. */
+rflbm_status rflbm_batch_step(rflbm_batch* b, int64_t nsteps);
+/* The same update with one single-box launch per replica and step (the
+ * reference the persistent form is measured against). */
+rflbm_status rflbm_batch_step_separate(rflbm_batch* b, int64_t nsteps);
+/* Waits; EUNSTABLE if any replica's instability flag is set. */
+rflbm_status rflbm_batch_sync(rflbm_batch* b);
+int64_t rflbm_batch_step_count(const rflbm_batch* b);
+/* Sets t for every replica (checkpoint restart of a batch). */
+rflbm_status rflbm_batch_set_step_count(rflbm_batch* b, int64_t t);
+/* Total nodes over all replicas. */
+int64_t rflbm_batch_nodes(const rflbm_batch* b);
+/* Launch shape: tile = nodes per work item (128 or 256, one thread per node),
+ * blocks_per_cu = size of the persistent grid per compute unit (0: one block
+ * per tile), graph_steps = steps per captured hipGraph (even, 0 = no graph).
+ * Results do not depend on the shape. */
+rflbm_status rflbm_batch_set_launch(rflbm_batch* b, int32_t tile, int32_t blocks_per_cu,
+                                    int32_t graph_steps);
+rflbm_status rflbm_batch_get_launch(const rflbm_batch* b, int32_t* tile, int32_t* blocks_per_cu,
+                                    int32_t* graph_steps);
+/* Times nsteps batch steps with HIP events on the batch stream. */
+rflbm_status rflbm_batch_time_steps(rflbm_batch* b, int64_t nsteps, double* ms);
+/* Picks the fastest launch shape by timing trial_steps (even) steps of each
+ * candidate (tile 128/256 x blocks per CU 0/2/4/8/16); the trial steps are
+ * ordinary steps of the simulation.  With a cache_path (text file, one line
+ * per batch signature: device, storage, rounds, replica boxes), a cached choice
+ * is applied without timing and new choices are appended.  The graph length is
+ * kept. */
+rflbm_status rflbm_batch_autotune(rflbm_batch* b, int32_t trial_steps, const char* cache_path);
 
 /* Diagnostics.
  * rflbm_rng_normals: for count nodes n = node0 .. node0 + count - 1 at step t,

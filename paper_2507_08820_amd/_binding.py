@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librflbm.so")
+LIB_PATH = os.environ.get("RFLBM_LIBRARY") or os.path.join(_HERE, "librflbm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "rflbm.h")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
@@ -90,7 +90,27 @@ _SIGS = {
     "rflbm_get_sk": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
                                     ctypes.POINTER(ctypes.c_int64)]),
     "rflbm_reset_sk": (ctypes.c_int, [_VP]),
+    "rflbm_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "rflbm_get_launch": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "rflbm_time_steps": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    "rflbm_batch_required_bytes": (ctypes.c_size_t, [ctypes.c_int32, _PP]),
+    "rflbm_batch_create": (ctypes.c_int, [ctypes.c_int32, _PP, _VP, ctypes.c_size_t, _VP,
+                                          ctypes.POINTER(_VP)]),
+    "rflbm_batch_destroy": (ctypes.c_int, [_VP]),
+    "rflbm_batch_lattice": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP)]),
+    "rflbm_batch_set_params": (ctypes.c_int, [_VP, ctypes.c_int32, _PP]),
+    "rflbm_batch_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
+    "rflbm_batch_step_separate": (ctypes.c_int, [_VP, ctypes.c_int64]),
+    "rflbm_batch_sync": (ctypes.c_int, [_VP]),
+    "rflbm_batch_step_count": (ctypes.c_int64, [_VP]),
+    "rflbm_batch_set_step_count": (ctypes.c_int, [_VP, ctypes.c_int64]),
+    "rflbm_batch_nodes": (ctypes.c_int64, [_VP]),
+    "rflbm_batch_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "rflbm_batch_get_launch": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]),
+    "rflbm_batch_time_steps": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    "rflbm_batch_autotune": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_char_p]),
     "rflbm_rng_normals": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP,
                                          _VP]),
@@ -184,11 +204,26 @@ class Lattice:
         check(self.lib.rflbm_create(ctypes.byref(self.params), _VP(self._ptr), nbytes,
                                     _VP(self.stream.cuda_stream), ctypes.byref(self._h)))
 
+    @classmethod
+    def _view(cls, batch, r, handle, dims, params):
+        """A borrowed replica of a Batch (released with the batch)."""
+        self = cls.__new__(cls)
+        self.lib = batch.lib
+        self.dims = tuple(dims)
+        self.n = int(np.prod(self.dims))
+        self.device = batch.device
+        self.params = params
+        self.stream = batch.stream
+        self._h = handle
+        self._batch = batch
+        self._owner = False
+        return self
+
     # -- life cycle --------------------------------------------------------
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
+        if getattr(self, "_owner", True) and getattr(self, "_h", None) and self._h.value:
             self.lib.rflbm_destroy(self._h)
-            self._h = _VP()
+        self._h = _VP()
 
     def __del__(self):
         try:
@@ -253,6 +288,14 @@ class Lattice:
     def sync(self):
         check(self.lib.rflbm_sync(self._h))
 
+    def set_launch(self, bx, xcd_remap=True):
+        check(self.lib.rflbm_set_launch(self._h, int(bx), int(bool(xcd_remap))))
+
+    def get_launch(self):
+        bx, remap = ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.rflbm_get_launch(self._h, ctypes.byref(bx), ctypes.byref(remap)))
+        return bx.value, bool(remap.value)
+
     def time_steps(self, nsteps) -> float:
         ms = ctypes.c_double()
         check(self.lib.rflbm_time_steps(self._h, int(nsteps), ctypes.byref(ms)))
@@ -285,6 +328,105 @@ class Lattice:
 
     def reset_sk(self):
         check(self.lib.rflbm_reset_sk(self._h))
+
+
+class Batch:
+    """Independent replicas (own box, taus, kT, rho0, seed, stream id) stepped
+    together by one persistent launch per step.  ``replicas`` is a list of
+    dicts with ``dims`` plus any keyword of make_params."""
+
+    def __init__(self, replicas, device="cuda", stream=None, **common):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.replicas = [dict(r) for r in replicas]
+        n = len(self.replicas)
+        arr = (Params * n)()
+        for i, r in enumerate(self.replicas):
+            kw = dict(common)
+            kw.update({k: v for k, v in r.items() if k != "dims"})
+            arr[i] = make_params(r["dims"], **kw)
+        self.params = arr
+        nbytes = self.lib.rflbm_batch_required_bytes(n, arr)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = _VP()
+        if nbytes == 0:
+            check(self.lib.rflbm_batch_create(n, arr, None, 0, None, ctypes.byref(self._h)))
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (_dev_ptr(self._buf) + 255) // 256 * 256
+        check(self.lib.rflbm_batch_create(n, arr, _VP(ptr), nbytes, _VP(self.stream.cuda_stream),
+                                          ctypes.byref(self._h)))
+        self.views = []
+        for i, r in enumerate(self.replicas):
+            h = _VP()
+            check(self.lib.rflbm_batch_lattice(self._h, i, ctypes.byref(h)))
+            self.views.append(Lattice._view(self, i, h, r["dims"], arr[i]))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            for v in self.views:
+                v._h = _VP()
+            self.lib.rflbm_batch_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.views)
+
+    def __getitem__(self, r):
+        return self.views[r]
+
+    @property
+    def t(self) -> int:
+        return int(self.lib.rflbm_batch_step_count(self._h))
+
+    @t.setter
+    def t(self, value):
+        check(self.lib.rflbm_batch_set_step_count(self._h, int(value)))
+
+    @property
+    def nodes(self) -> int:
+        return int(self.lib.rflbm_batch_nodes(self._h))
+
+    def set_params(self, r, **kw):
+        p = make_params(self.replicas[r]["dims"], **kw)
+        check(self.lib.rflbm_batch_set_params(self._h, int(r), ctypes.byref(p)))
+        self.views[r].params = p
+
+    def step(self, nsteps=1):
+        check(self.lib.rflbm_batch_step(self._h, int(nsteps)))
+
+    def step_separate(self, nsteps=1):
+        check(self.lib.rflbm_batch_step_separate(self._h, int(nsteps)))
+
+    def sync(self):
+        check(self.lib.rflbm_batch_sync(self._h))
+
+    def set_launch(self, tile=256, blocks_per_cu=8, graph_steps=0):
+        check(self.lib.rflbm_batch_set_launch(self._h, int(tile), int(blocks_per_cu),
+                                              int(graph_steps)))
+
+    def get_launch(self):
+        t, b, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.rflbm_batch_get_launch(self._h, ctypes.byref(t), ctypes.byref(b),
+                                              ctypes.byref(g)))
+        return t.value, b.value, g.value
+
+    def time_steps(self, nsteps) -> float:
+        ms = ctypes.c_double()
+        check(self.lib.rflbm_batch_time_steps(self._h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
+
+    def autotune(self, trial_steps=10, cache_path=None):
+        check(self.lib.rflbm_batch_autotune(self._h, int(trial_steps),
+                                            None if cache_path is None else
+                                            str(cache_path).encode()))
+        return self.get_launch()
 
 
 def rng_normals(seed, stream_id, rounds, node0, count, t, device="cuda"):

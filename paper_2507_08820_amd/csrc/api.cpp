@@ -14,6 +14,7 @@
 #include "../../include/rflbm.h"
 #include "d3q27.hpp"
 #include "kernels.hpp"
+#include "lattice.hpp"
 #include "storage.hpp"
 
 namespace rflbm {
@@ -27,37 +28,28 @@ namespace {
 
 thread_local std::string g_last_error;
 
+constexpr double kCs2 = 1.0 / 3.0;
+// Supported block shapes of the step kernel: (bx, 256 / bx).
+constexpr uint32_t kBlockX[3] = {64, 128, 256};
+
+bool valid_tau(double t) { return std::isfinite(t) && t > 0.5; }
+
+double fdt(double omega) { return std::sqrt(omega * (2.0 - omega)); }
+
+}  // namespace
+
+namespace rflbm {
+
 rflbm_status fail(rflbm_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
 }
 
-#define RFLBM_HIP(call)                                                                     \
-  do {                                                                                      \
-    const hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(RFLBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
-  } while (0)
-
-constexpr double kCs2 = 1.0 / 3.0;
-constexpr size_t kAlign = 256;
-// Supported block shapes of the step kernel: (bx, 256 / bx).
-constexpr uint32_t kBlockX[3] = {64, 128, 256};
-
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Layout {
-  uint64_t pitch;       // elements per plane
-  size_t pop_bytes;
-  size_t flag_off, acc_off, partial_off, scratch_off, total;
-  uint32_t grid_max;
-};
 
 uint64_t node_count(const rflbm_params& p) {
   return static_cast<uint64_t>(p.nx) * static_cast<uint64_t>(p.ny) * static_cast<uint64_t>(p.nz);
 }
-
-bool valid_tau(double t) { return std::isfinite(t) && t > 0.5; }
 
 std::string validate(const rflbm_params* p) {
   if (!p) return "params is NULL";
@@ -101,30 +93,7 @@ Layout layout_for(const rflbm_params& p) {
   return L;
 }
 
-double fdt(double omega) { return std::sqrt(omega * (2.0 - omega)); }
-
-}  // namespace
-
-struct rflbm_lattice {
-  rflbm_params p;
-  Layout L;
-  uint8_t* buf = nullptr;
-  bool owns_buf = false;
-  hipStream_t stream = nullptr;
-  int64_t t = 0;
-  int32_t stats_every = 0;
-  Launch launch{};
-  bool xcd_remap = true;
-  // S(k) state (library-allocated on first use)
-  hipfftHandle plan = 0;
-  bool have_plan = false;
-  float* sk_fields = nullptr;   // 10 N floats
-  void* sk_spec = nullptr;      // nz ny (nx/2 + 1) complex
-  double* sk_sums = nullptr;    // 10 nshells
-  unsigned long long* sk_counts = nullptr;  // nshells
-  int64_t sk_samples = 0;
-  int32_t nshells = 0;
-};
+}  // namespace rflbm
 
 namespace {
 
@@ -152,6 +121,10 @@ GatherArgs gather_args(const rflbm_lattice* L, const rflbm_params& p, int64_t t)
   sigma_of(p, g.sigma, g.inv_sigma);
   return g;
 }
+
+}  // namespace
+
+namespace rflbm {
 
 StepArgs step_args(const rflbm_lattice* L) {
   const rflbm_params& p = L->p;
@@ -192,6 +165,39 @@ StepArgs step_args(const rflbm_lattice* L) {
   return a;
 }
 
+void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStream_t s) {
+  L->p = p;
+  L->L = layout_for(p);
+  L->buf = buf;
+  L->stream = s;
+  L->launch = make_launch(p.nx, p.ny, p.nz, p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64),
+                          p.nx >= 256 ? 1 : (p.nx >= 128 ? 2 : 4));
+}
+
+hipError_t lattice_clear(rflbm_lattice* L) {
+  // populations (deviation 0 = rest at rho0), flag and accumulators
+  return hipMemsetAsync(L->buf, 0, L->L.scratch_off, L->stream);
+}
+
+void lattice_release(rflbm_lattice* L) {
+  if (L->have_plan) (void)hipfftDestroy(L->plan);
+  if (L->sk_fields) (void)hipFree(L->sk_fields);
+  if (L->sk_spec) (void)hipFree(L->sk_spec);
+  if (L->sk_sums) (void)hipFree(L->sk_sums);
+  if (L->sk_counts) (void)hipFree(L->sk_counts);
+  if (L->owns_buf) (void)hipFree(L->buf);
+  L->have_plan = false;
+  L->sk_fields = nullptr;
+  L->sk_spec = nullptr;
+  L->sk_sums = nullptr;
+  L->sk_counts = nullptr;
+  L->buf = nullptr;
+}
+
+}  // namespace rflbm
+
+namespace {
+
 rflbm_status check_lattice(const rflbm_lattice* L) {
   if (!L) return fail(RFLBM_EINVAL, "lattice is NULL");
   return RFLBM_OK;
@@ -225,6 +231,57 @@ rflbm_status stage_in(const void* src, size_t bytes, bool is_host, hipStream_t s
 }
 
 }  // namespace
+
+namespace rflbm {
+
+rflbm_status lattice_set_params(rflbm_lattice* L, const rflbm_params* p) {
+  const std::string err = validate(p);
+  if (!err.empty()) return fail(RFLBM_EINVAL, err);
+  if (p->nx != L->p.nx || p->ny != L->p.ny || p->nz != L->p.nz || p->storage != L->p.storage)
+    return fail(RFLBM_EINVAL, "box size and storage type are fixed at creation");
+  const GatherArgs from = gather_args(L, L->p, L->t);
+  const GatherArgs to = gather_args(L, *p, L->t);
+  const bool reencode = from.rho0 != to.rho0 || std::memcmp(from.sigma, to.sigma, sizeof(from.sigma)) != 0;
+  if (reencode) RFLBM_HIP(launch_reencode(L->p.storage, from, to, L->stream));
+  L->p = *p;
+  return RFLBM_OK;
+}
+
+rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps) {
+  if (nsteps < 0) return fail(RFLBM_EINVAL, "nsteps must be >= 0");
+  StepArgs a = step_args(L);
+  const int rounds = L->p.kT > 0.0 ? static_cast<int>(L->p.philox_rounds) : 0;
+  double* acc = reinterpret_cast<double*>(L->buf + L->L.acc_off);
+  double* scratch = reinterpret_cast<double*>(L->buf + L->L.scratch_off);
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int64_t t = L->t;
+    const bool stats = L->stats_every > 0 && (t % L->stats_every) == 0;
+    a.step = static_cast<uint32_t>(t & 0xffffffffu);
+    RFLBM_HIP(launch_step(L->p.storage, (t & 1) != 0, rounds, stats, a, L->launch, L->stream));
+    if (stats) RFLBM_HIP(launch_stats_reduce(a.partials, L->launch.grid, scratch, acc, L->stream));
+    L->t = t + 1;
+  }
+  return RFLBM_OK;
+}
+
+rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t) {
+  if (t < 0) return fail(RFLBM_EINVAL, "step count must be >= 0");
+  if ((t & 1) != (L->t & 1)) {
+    // the storage layout depends on the parity: move the state to the new one
+    const uint64_t N = nodes(L);
+    double* tmp = nullptr;
+    RFLBM_HIP(hipMalloc(&tmp, 27 * N * sizeof(double)));
+    hipError_t e = launch_get_populations(L->p.storage, gather_args(L, L->p, L->t), tmp, L->stream);
+    if (e == hipSuccess) e = launch_set_populations(L->p.storage, gather_args(L, L->p, t), tmp, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("re-layout: ") + hipGetErrorString(e));
+  }
+  L->t = t;
+  return RFLBM_OK;
+}
+
+}  // namespace rflbm
 
 extern "C" {
 
@@ -265,27 +322,21 @@ rflbm_status rflbm_create(const rflbm_params* p, void* dev_buf, size_t bytes, vo
     return fail(RFLBM_EINVAL, "caller buffer must be 256-byte aligned");
   rflbm_lattice* L = new (std::nothrow) rflbm_lattice();
   if (!L) return fail(RFLBM_ENOMEM, "host allocation failed");
-  L->p = *p;
-  L->L = lay;
-  L->stream = static_cast<hipStream_t>(hip_stream);
-  L->launch = make_launch(p->nx, p->ny, p->nz, p->nx >= 256 ? 256 : (p->nx >= 128 ? 128 : 64),
-                          p->nx >= 256 ? 1 : (p->nx >= 128 ? 2 : 4));
-  if (dev_buf) {
-    L->buf = static_cast<uint8_t*>(dev_buf);
-  } else {
+  uint8_t* buf = static_cast<uint8_t*>(dev_buf);
+  if (!buf) {
     void* b = nullptr;
     const hipError_t e = hipMalloc(&b, lay.total);
     if (e != hipSuccess) {
       delete L;
       return fail(RFLBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
-    L->buf = static_cast<uint8_t*>(b);
+    buf = static_cast<uint8_t*>(b);
     L->owns_buf = true;
   }
-  // zero the flag, accumulators and the populations (deviation 0 = rest at rho0)
-  hipError_t e = hipMemsetAsync(L->buf, 0, lay.scratch_off, L->stream);
+  lattice_init(L, *p, buf, static_cast<hipStream_t>(hip_stream));
+  const hipError_t e = lattice_clear(L);
   if (e != hipSuccess) {
-    if (L->owns_buf) (void)hipFree(L->buf);
+    lattice_release(L);
     delete L;
     return fail(RFLBM_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
   }
@@ -295,30 +346,20 @@ rflbm_status rflbm_create(const rflbm_params* p, void* dev_buf, size_t bytes, vo
 
 rflbm_status rflbm_destroy(rflbm_lattice* L) {
   if (!L) return RFLBM_OK;
+  if (L->is_view) return fail(RFLBM_ESTATE, "a replica view is released with its batch");
   (void)hipStreamSynchronize(L->stream);
-  if (L->have_plan) (void)hipfftDestroy(L->plan);
-  if (L->sk_fields) (void)hipFree(L->sk_fields);
-  if (L->sk_spec) (void)hipFree(L->sk_spec);
-  if (L->sk_sums) (void)hipFree(L->sk_sums);
-  if (L->sk_counts) (void)hipFree(L->sk_counts);
-  if (L->owns_buf) (void)hipFree(L->buf);
+  lattice_release(L);
   delete L;
   return RFLBM_OK;
 }
 
 rflbm_status rflbm_set_params(rflbm_lattice* L, const rflbm_params* p) {
   if (rflbm_status s = check_lattice(L)) return s;
-  const std::string err = validate(p);
-  if (!err.empty()) return fail(RFLBM_EINVAL, err);
-  if (p->nx != L->p.nx || p->ny != L->p.ny || p->nz != L->p.nz || p->storage != L->p.storage)
-    return fail(RFLBM_EINVAL, "box size and storage type are fixed at creation");
-  const GatherArgs from = gather_args(L, L->p, L->t);
-  const GatherArgs to = gather_args(L, *p, L->t);
-  const bool reencode = from.rho0 != to.rho0 || std::memcmp(from.sigma, to.sigma, sizeof(from.sigma)) != 0;
-  if (reencode) RFLBM_HIP(launch_reencode(L->p.storage, from, to, L->stream));
-  L->p = *p;
-  return RFLBM_OK;
+  if (L->is_view) return fail(RFLBM_ESTATE, "replicas of a batch change parameters with rflbm_batch_set_params");
+  return lattice_set_params(L, p);
 }
+
+
 
 rflbm_status rflbm_get_params(const rflbm_lattice* L, rflbm_params* p) {
   if (rflbm_status s = check_lattice(L)) return s;
@@ -341,26 +382,12 @@ rflbm_status rflbm_init_equilibrium(rflbm_lattice* L, const double* rho, const d
   return RFLBM_OK;
 }
 
-static rflbm_status do_steps(rflbm_lattice* L, int64_t nsteps) {
-  if (nsteps < 0) return fail(RFLBM_EINVAL, "nsteps must be >= 0");
-  StepArgs a = step_args(L);
-  const int rounds = L->p.kT > 0.0 ? static_cast<int>(L->p.philox_rounds) : 0;
-  double* acc = reinterpret_cast<double*>(L->buf + L->L.acc_off);
-  double* scratch = reinterpret_cast<double*>(L->buf + L->L.scratch_off);
-  for (int64_t s = 0; s < nsteps; ++s) {
-    const int64_t t = L->t;
-    const bool stats = L->stats_every > 0 && (t % L->stats_every) == 0;
-    a.step = static_cast<uint32_t>(t & 0xffffffffu);
-    RFLBM_HIP(launch_step(L->p.storage, (t & 1) != 0, rounds, stats, a, L->launch, L->stream));
-    if (stats) RFLBM_HIP(launch_stats_reduce(a.partials, L->launch.grid, scratch, acc, L->stream));
-    L->t = t + 1;
-  }
-  return RFLBM_OK;
-}
+
 
 rflbm_status rflbm_step(rflbm_lattice* L, int64_t nsteps) {
   if (rflbm_status s = check_lattice(L)) return s;
-  return do_steps(L, nsteps);
+  if (L->is_view) return fail(RFLBM_ESTATE, "replicas of a batch are stepped with rflbm_batch_step");
+  return lattice_steps(L, nsteps);
 }
 
 rflbm_status rflbm_sync(rflbm_lattice* L) {
@@ -376,21 +403,11 @@ int64_t rflbm_step_count(const rflbm_lattice* L) { return L ? L->t : -1; }
 
 rflbm_status rflbm_set_step_count(rflbm_lattice* L, int64_t t) {
   if (rflbm_status s = check_lattice(L)) return s;
-  if (t < 0) return fail(RFLBM_EINVAL, "step count must be >= 0");
-  if ((t & 1) != (L->t & 1)) {
-    // the storage layout depends on the parity: move the state to the new one
-    const uint64_t N = nodes(L);
-    double* tmp = nullptr;
-    RFLBM_HIP(hipMalloc(&tmp, 27 * N * sizeof(double)));
-    hipError_t e = launch_get_populations(L->p.storage, gather_args(L, L->p, L->t), tmp, L->stream);
-    if (e == hipSuccess) e = launch_set_populations(L->p.storage, gather_args(L, L->p, t), tmp, L->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    (void)hipFree(tmp);
-    if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("re-layout: ") + hipGetErrorString(e));
-  }
-  L->t = t;
-  return RFLBM_OK;
+  if (L->is_view) return fail(RFLBM_ESTATE, "replicas of a batch share the batch's step count");
+  return lattice_set_step_count(L, t);
 }
+
+
 
 rflbm_status rflbm_get_populations(rflbm_lattice* L, double* dst, int dst_is_host) {
   if (rflbm_status s = check_lattice(L)) return s;
@@ -553,8 +570,24 @@ rflbm_status rflbm_reset_sk(rflbm_lattice* L) {
   return RFLBM_OK;
 }
 
+rflbm_status rflbm_set_launch(rflbm_lattice* L, int32_t bx, int32_t xcd_remap) {
+  if (rflbm_status s = check_lattice(L)) return s;
+  if (bx != 64 && bx != 128 && bx != 256) return fail(RFLBM_EINVAL, "bx must be 64, 128 or 256");
+  L->launch = make_launch(L->p.nx, L->p.ny, L->p.nz, bx, 256 / bx);
+  L->xcd_remap = xcd_remap != 0;
+  return RFLBM_OK;
+}
+
+rflbm_status rflbm_get_launch(const rflbm_lattice* L, int32_t* bx, int32_t* xcd_remap) {
+  if (rflbm_status s = check_lattice(L)) return s;
+  if (bx) *bx = static_cast<int32_t>(L->launch.bx);
+  if (xcd_remap) *xcd_remap = L->xcd_remap ? 1 : 0;
+  return RFLBM_OK;
+}
+
 rflbm_status rflbm_time_steps(rflbm_lattice* L, int64_t nsteps, double* ms) {
   if (rflbm_status s = check_lattice(L)) return s;
+  if (L->is_view) return fail(RFLBM_ESTATE, "replicas of a batch are timed with rflbm_batch_time_steps");
   if (!ms) return fail(RFLBM_EINVAL, "ms is NULL");
   hipEvent_t e0, e1;
   RFLBM_HIP(hipEventCreate(&e0));
@@ -562,7 +595,7 @@ rflbm_status rflbm_time_steps(rflbm_lattice* L, int64_t nsteps, double* ms) {
   rflbm_status st = RFLBM_OK;
   hipError_t e = hipEventRecord(e0, L->stream);
   if (e == hipSuccess) {
-    st = do_steps(L, nsteps);
+    st = lattice_steps(L, nsteps);
     e = hipEventRecord(e1, L->stream);
   }
   if (e == hipSuccess) e = hipEventSynchronize(e1);

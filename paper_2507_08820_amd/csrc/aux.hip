@@ -182,16 +182,34 @@ __global__ void rng_kernel(uint32_t key0, uint32_t key1, uint32_t sid, uint32_t 
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-__global__ void copy_kernel(u32x4* __restrict__ dst, const u32x4* __restrict__ src, uint64_t n) {
-  for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < n;
-       e += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-    __builtin_nontemporal_store(src[e], dst + e);
+// Each block moves 1024 16-byte vectors (16 KiB): four coalesced loads per
+// thread issued before the four stores.
+constexpr uint32_t kCopyVecPerBlock = 1024;
+
+__global__ void __launch_bounds__(256) copy_kernel(u32x4* __restrict__ dst, const u32x4* __restrict__ src,
+                                                   uint64_t n) {
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kCopyVecPerBlock + threadIdx.x;
+  u32x4 r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t e = base + k * 256;
+    if (e < n) r[k] = __builtin_nontemporal_load(src + e);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t e = base + k * 256;
+    if (e < n) __builtin_nontemporal_store(r[k], dst + e);
+  }
 }
 
 __global__ void fill_zero_kernel(double* dst, uint64_t n) {
   for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < n;
        e += static_cast<uint64_t>(gridDim.x) * blockDim.x)
     dst[e] = 0.0;
+}
+
+__global__ void set_u32_kernel(uint32_t* dst, uint32_t value) {
+  if (threadIdx.x == 0) *dst = value;
 }
 
 uint32_t grid_for(uint64_t work, uint32_t block) {
@@ -260,8 +278,15 @@ hipError_t launch_rng_normals(uint32_t key0, uint32_t key1, uint32_t stream_id, 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const uint64_t n = bytes / sizeof(u32x4);
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256) < 8192 ? grid_for(n, 256) : 8192), dim3(256),
-                     0, s, static_cast<u32x4*>(dst), static_cast<const u32x4*>(src), n);
+  const uint64_t blocks = (n + kCopyVecPerBlock - 1) / kCopyVecPerBlock;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
+                     static_cast<u32x4*>(dst), static_cast<const u32x4*>(src), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u32(uint32_t* dst, uint32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, s, dst, value);
   return hipGetLastError();
 }
 

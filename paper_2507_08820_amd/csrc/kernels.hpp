@@ -15,6 +15,8 @@
 #include <cstdint>
 #include <hip/hip_runtime.h>
 
+#include "fastdiv.hpp"
+
 namespace rflbm {
 
 enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
@@ -47,6 +49,31 @@ struct StepArgs {
   int* flag;             // set to 1 on rho <= 0 or non-finite rho, j
   double* partials;      // statistics partials, column-major [kNumStats][gridDim.x]
 };
+
+// One replica of a batch: its lattice arguments plus what the batched kernel
+// needs to turn a tile-local flattened node index into (x, y, z).
+struct ReplicaArgs {
+  StepArgs a;        // layout and physics of the replica (tiling fields unused)
+  uint32_t tile0;    // first tile of the replica in the batch's tile list
+  uint32_t nodes;    // nx * ny * nz
+  FastDiv div_x;     // division by nx
+  FastDiv div_xy;    // division by nx * ny
+};
+
+struct BatchArgs {
+  const ReplicaArgs* __restrict__ reps;  // device table, one entry per replica
+  const uint32_t* __restrict__ tile_rep; // replica of each tile
+  uint32_t ntiles;                       // tiles of blockDim.x consecutive nodes, all replicas
+  const uint32_t* step;                  // device step counter (t mod 2^32)
+};
+
+// One step of every replica (persistent grid of `grid` blocks walking the tiles);
+// the Philox step counter is read from b.step on the device, the parity `odd`
+// must match it.
+hipError_t launch_batch_step(int storage, bool odd, int rounds, const BatchArgs& b, uint32_t grid,
+                             uint32_t tile, hipStream_t stream);
+// *step += 1 on the device (a graph node after each captured batch step).
+hipError_t launch_advance_step(uint32_t* step, hipStream_t stream);
 
 // Launch configuration of the step kernel.
 struct Launch {
@@ -95,5 +122,7 @@ hipError_t launch_rng_normals(uint32_t key0, uint32_t key1, uint32_t stream_id, 
                               hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_fill_zero(double* dst, size_t n, hipStream_t s);
+// *dst = value (one thread), stream ordered.
+hipError_t launch_set_u32(uint32_t* dst, uint32_t value, hipStream_t s);
 
 }  // namespace rflbm

@@ -1,0 +1,79 @@
+// lattice.hpp -- internal state of a lattice object and the helpers shared by
+// the single-box interface (api.cpp) and the batched one (batch.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/rflbm.h"
+#include "kernels.hpp"
+
+namespace rflbm {
+
+// Device buffer of one lattice: 27 population planes, then the instability
+// flag, the FP64 accumulators, the statistics partials and reduction scratch.
+struct Layout {
+  uint64_t pitch;  // elements per plane
+  size_t pop_bytes;
+  size_t flag_off, acc_off, partial_off, scratch_off, total;
+  uint32_t grid_max;
+};
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a);
+uint64_t node_count(const rflbm_params& p);
+std::string validate(const rflbm_params* p);
+Layout layout_for(const rflbm_params& p);
+rflbm_status fail(rflbm_status st, const std::string& msg);
+
+}  // namespace rflbm
+
+struct rflbm_lattice {
+  rflbm_params p;
+  rflbm::Layout L;
+  uint8_t* buf = nullptr;
+  bool owns_buf = false;
+  bool is_view = false;  // a replica of a batch (borrowed, destroyed with the batch)
+  hipStream_t stream = nullptr;
+  int64_t t = 0;
+  int32_t stats_every = 0;
+  rflbm::Launch launch{};
+  bool xcd_remap = true;
+  // S(k) state (library-allocated on first use)
+  hipfftHandle plan = 0;
+  bool have_plan = false;
+  float* sk_fields = nullptr;               // 10 N floats
+  void* sk_spec = nullptr;                  // nz ny (nx/2 + 1) complex
+  double* sk_sums = nullptr;                // 10 nshells
+  unsigned long long* sk_counts = nullptr;  // nshells
+  int64_t sk_samples = 0;
+  int32_t nshells = 0;
+};
+
+namespace rflbm {
+
+// Kernel arguments of one step of lattice L (everything but the step count).
+StepArgs step_args(const rflbm_lattice* L);
+// Sets up a lattice object on an existing buffer (no allocation, no kernels).
+void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStream_t s);
+// Zeroes the populations (rest state), flag and accumulators of L.
+hipError_t lattice_clear(rflbm_lattice* L);
+// Releases what the library allocated for L (S(k) scratch, owned buffer).
+void lattice_release(rflbm_lattice* L);
+// The single-lattice operations without the checks that keep batch replicas
+// consistent (the batch calls these for its replicas).
+rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps);
+rflbm_status lattice_set_params(rflbm_lattice* L, const rflbm_params* p);
+rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t);
+
+}  // namespace rflbm
+
+#define RFLBM_HIP(call)                                                                     \
+  do {                                                                                      \
+    const hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                                   \
+      return ::rflbm::fail(RFLBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+  } while (0)

@@ -2,7 +2,7 @@
 // lattice Boltzmann method on D3Q27 (arXiv:2507.08820, Eq. r-flbe2), and the
 // deterministic reduction of its ensemble statistics (Sec. III).
 //
-// One thread updates one node:
+// One thread updates one node (the body is in node_body.inc):
 //   1. gather the 27 populations arriving at x (AA pattern, see kernels.hpp);
 //   2. project them on the Table II Hermite modes (Eq. moments) with three
 //      3-point sweeps (d3q27.hpp);
@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "d3q27.hpp"
+#include "fastdiv.hpp"
 #include "kernels.hpp"
 #include "philox.hpp"
 #include "storage.hpp"
@@ -31,11 +32,41 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Cache policy of the population accesses, per step parity.  The even step
+// reads and writes each node's own slots: nothing is reused, so its loads are
+// marked non-temporal.  The odd step reads and writes slots shifted by +-1 in
+// x; neighbouring waves share the boundary cache lines, so its accesses keep
+// the default policy and meet in L2.
+#ifndef RFLBM_EVEN_LOAD_NT
+#define RFLBM_EVEN_LOAD_NT 1
+#endif
+#ifndef RFLBM_EVEN_STORE_NT
+#define RFLBM_EVEN_STORE_NT 1
+#endif
+#ifndef RFLBM_ODD_LOAD_NT
+#define RFLBM_ODD_LOAD_NT 0
+#endif
+#ifndef RFLBM_ODD_STORE_NT
+#define RFLBM_ODD_STORE_NT 0
+#endif
+
+template <bool ODD, class P>
+__device__ __forceinline__ auto load_pop(P p) {
+  if constexpr (ODD ? RFLBM_ODD_LOAD_NT : RFLBM_EVEN_LOAD_NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
+template <bool ODD, class T, class P>
+__device__ __forceinline__ void store_pop(T v, P p) {
+  if constexpr (ODD ? RFLBM_ODD_STORE_NT : RFLBM_EVEN_STORE_NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// One box: a block covers bx x by nodes of one z plane (blockDim = (bx, by)).
 template <int S, bool ODD, int ROUNDS, bool STATS>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
-  using C = Codec<S>;
-  using T = typename C::T;
-
   uint32_t tile = blockIdx.x;
   if (a.xcd_remap) tile = (tile & 7u) * (gridDim.x >> 3) + (tile >> 3);
   const uint32_t tx = tile % a.tiles_x;
@@ -47,137 +78,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
   const uint32_t tid = threadIdx.x + blockDim.x * threadIdx.y;
   const bool active = tile < a.ntiles && x < a.nx && y < a.ny;
 
-  __shared__ float stat_lds[STATS ? kNumStats : 1][STATS ? kBlock : 1];
+  __shared__ float stat_lds[STATS ? kNumStats : 1][kBlock];
 
   if (active) {
-    const uint32_t nx = a.nx, ny = a.ny, nz = a.nz, sxy = nx * ny;
-    // byte offsets of the three x, y, z coordinates x - 1, x, x + 1 (periodic)
-    uint32_t X[3], Y[3], Z[3];
-    X[0] = wrap_add(x, -1, nx) * sizeof(T);
-    X[1] = x * sizeof(T);
-    X[2] = wrap_add(x, 1, nx) * sizeof(T);
-    Y[0] = wrap_add(y, -1, ny) * nx * sizeof(T);
-    Y[1] = y * nx * sizeof(T);
-    Y[2] = wrap_add(y, 1, ny) * nx * sizeof(T);
-    Z[0] = wrap_add(z, -1, nz) * sxy * sizeof(T);
-    Z[1] = z * sxy * sizeof(T);
-    Z[2] = wrap_add(z, 1, nz) * sxy * sizeof(T);
-    const uint64_t plane_bytes = a.pitch * sizeof(T);
-    char* const base = static_cast<char*>(a.pop);
-
-    // 1. gather
-    float v[kQ];
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
-      const int plane = ODD ? kQ - 1 - i : i;
-      const uint32_t off = ODD ? X[2 - ix] + Y[2 - iy] + Z[2 - iz] : X[1] + Y[1] + Z[1];
-      const T q = *reinterpret_cast<const T*>(base + plane * plane_bytes + off);
-      v[i] = C::decode(q, a.sigma[speed_class(i)]);
-    }
-
-    // 2. Hermite projection (deviation form: slot 0 holds rho - rho0)
-    forward27(v);
-    const float rho = a.rho0 + v[0];
-    const float inv_rho = __builtin_amdgcn_rcpf(rho);
-    const float ux = v[1] * inv_rho, uy = v[3] * inv_rho, uz = v[9] * inv_rho;
-    if (!(rho > 0.0f) || !(fabsf(ux) + fabsf(uy) + fabsf(uz) < 1.0e30f)) *a.flag = 1;
-
-    // 3. statistics of the pre-collision state
-    if constexpr (STATS) {
-      const float s[kNumStats] = {
-          v[0], v[0] * v[0],
-          v[1], v[3], v[9], v[1] * v[1], v[3] * v[3], v[9] * v[9],
-          ux * ux, uy * uy, uz * uz,
-          v[2], v[6], v[18], v[4], v[10], v[12],
-          v[2] * v[2], v[6] * v[6], v[18] * v[18], v[4] * v[4], v[10] * v[10], v[12] * v[12]};
-#pragma unroll
-      for (int c = 0; c < kNumStats; ++c) stat_lds[c][tid] = s[c];
-    }
-
-    // 4. equilibrium modes m_eq(px, py, pz) = exy[px + 3 py] * ez[pz]
-    float exy[9];
-    {
-      const float ex[3] = {1.0f, ux, ux * ux};
-      const float ey[3] = {1.0f, uy, uy * uy};
-#pragma unroll
-      for (int py = 0; py < 3; ++py)
-#pragma unroll
-        for (int px = 0; px < 3; ++px) exy[px + 3 * py] = ex[px] * ey[py];
-    }
-    const float ez[3] = {rho, rho * uz, rho * uz * uz};
-    auto meq = [&](int slot) -> float { return slot < 9 ? exy[slot] * rho : exy[slot % 9] * ez[slot / 9]; };
-
-    // 5. relaxation of the non-equilibrium modes
-    {
-      const int sxx = mode_slot(4), syy = mode_slot(5), szz = mode_slot(6);
-      const float exx = meq(sxx), eyy = meq(syy), ezz = meq(szz);
-      const float axx = v[sxx] - exx, ayy = v[syy] - eyy, azz = v[szz] - ezz;
-      const float tr = (axx + ayy + azz) * (1.0f / 3.0f) * a.lam_b_minus_s;
-      v[sxx] = exx + fmaf(a.lam_s, axx, tr);
-      v[syy] = eyy + fmaf(a.lam_s, ayy, tr);
-      v[szz] = ezz + fmaf(a.lam_s, azz, tr);
-    }
-#pragma unroll
-    for (int k = 7; k <= 9; ++k) {
-      const int s = mode_slot(k);
-      const float e = meq(s);
-      v[s] = fmaf(a.lam_s, v[s] - e, e);
-    }
-#pragma unroll
-    for (int k = 10; k < kQ; ++k) {
-      const int s = mode_slot(k);
-      const float e = meq(s);
-      v[s] = fmaf(a.lam_g[k - 10], v[s] - e, e);
-    }
-
-    // 6. noise phi_k r_k, phi_k = sqrt(rho) * amp_k
-    if constexpr (ROUNDS > 0) {
-      const float srho = __builtin_amdgcn_sqrtf(rho);
-      const uint32_t node = (X[1] + Y[1] + Z[1]) / sizeof(T);
-#pragma unroll
-      for (uint32_t j = 0; j < 6; ++j) {
-        const Word4 w = philox<ROUNDS>(Word4{node, a.step, j, a.stream_id}, a.key0, a.key1);
-        float r[4];
-        box_muller(w.w0, w.w1, r[0], r[1]);
-        box_muller(w.w2, w.w3, r[2], r[3]);
-        if (j == 0) {
-          const float rbar = (r[0] + r[1] + r[2]) * (1.0f / 3.0f);
-          const float tr = srho * a.amp_b_minus_s * rbar;
-          const float sd = srho * a.amp_s;
-          v[mode_slot(4)] += fmaf(sd, r[0], tr);
-          v[mode_slot(5)] += fmaf(sd, r[1], tr);
-          v[mode_slot(6)] += fmaf(sd, r[2], tr);
-          v[mode_slot(7)] = fmaf(srho * a.amp_off, r[3], v[mode_slot(7)]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int k = 4 + 4 * static_cast<int>(j) + q;
-            if (k < kQ) {
-              const float amp = k <= 9 ? a.amp_off : a.amp_g[k - 10];
-              v[mode_slot(k)] = fmaf(srho * amp, r[q], v[mode_slot(k)]);
-            }
-          }
-        }
-      }
-    }
-
-    // 7. back to populations (slot 0 still holds rho - rho0) and scatter
-    inverse27(v);
-    // The even step stores at the offset it loaded from.  Hiding that equality
-    // from the compiler keeps it from holding 27 64-bit load addresses live
-    // across the collision; every access then uses a scalar plane base plus a
-    // 32-bit vector offset.
-    uint32_t own = X[1] + Y[1] + Z[1];
-    if constexpr (!ODD) asm volatile("" : "+v"(own));
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
-      const int plane = ODD ? i : kQ - 1 - i;
-      const uint32_t off = ODD ? X[ix] + Y[iy] + Z[iz] : own;
-      T* dst = reinterpret_cast<T*>(base + plane * plane_bytes + off);
-      __builtin_nontemporal_store(C::encode(v[i], a.inv_sigma[speed_class(i)]), dst);
-    }
+    const uint32_t step = a.step;
+#include "node_body.inc"
   } else if constexpr (STATS) {
 #pragma unroll
     for (int c = 0; c < kNumStats; ++c) stat_lds[c][tid] = 0.0f;
@@ -202,6 +107,43 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
       a.partials[static_cast<size_t>(tid) * gridDim.x + blockIdx.x] = acc;
     }
   }
+}
+
+// Many boxes: tile t holds blockDim.x consecutive nodes (flattened index) of
+// replica tile_rep[t]; a persistent grid walks the tiles.  The step count (the
+// Philox counter) comes from device memory so that a captured graph of several
+// steps can be replayed; the parity is a template parameter, and the host only
+// replays graphs of an even number of steps from an even step count.
+template <int S, bool ODD, int ROUNDS>
+__global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
+  constexpr bool STATS = false;
+  float (*stat_lds)[kBlock] = nullptr;
+  const uint32_t tid = 0;
+  // the tables are read-only for the whole launch: constant address space,
+  // so the per-tile lookups are scalar loads
+  typedef __attribute__((address_space(4))) const ReplicaArgs CReps;
+  typedef __attribute__((address_space(4))) const uint32_t CU32;
+  CReps* const reps = (CReps*)(b.reps);
+  CU32* const tile_rep = (CU32*)(b.tile_rep);
+  const uint32_t step = *(CU32*)(b.step);
+  for (uint32_t tile = blockIdx.x; tile < b.ntiles; tile += gridDim.x) {
+    CReps& r = reps[tile_rep[tile]];
+    __attribute__((address_space(4))) const StepArgs& a = r.a;
+    const uint32_t n = (tile - r.tile0) * blockDim.x + threadIdx.x;
+    if (n < r.nodes) {
+      const uint32_t z = fast_div(n, FastDiv{r.div_xy.m, r.div_xy.s});
+      const uint32_t rem = n - z * (a.nx * a.ny);
+      const uint32_t y = fast_div(rem, FastDiv{r.div_x.m, r.div_x.s});
+      const uint32_t x = rem - y * a.nx;
+#include "node_body.inc"
+    }
+  }
+  (void)stat_lds;
+  (void)tid;
+}
+
+__global__ void advance_step(uint32_t* step) {
+  if (threadIdx.x == 0) *step += 1u;
 }
 
 // Sums 2048 consecutive entries of one column per block (fixed order).
@@ -283,6 +225,39 @@ hipError_t launch_step(int storage, bool odd, int rounds, bool stats, const Step
     case kBF16: return launch_s<kBF16>(odd, rounds, stats, a, l, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_batch_step(int storage, bool odd, int rounds, const BatchArgs& b, uint32_t grid,
+                             uint32_t tile, hipStream_t stream) {
+  if (tile != 128 && tile != 256) return hipErrorInvalidConfiguration;
+  const dim3 g(grid), blk(tile);
+#define RFLBM_BATCH_R(S, O)                                                                    \
+  switch (rounds) {                                                                            \
+    case 0: hipLaunchKernelGGL((batch_kernel<S, O, 0>), g, blk, 0, stream, b); break;          \
+    case 7: hipLaunchKernelGGL((batch_kernel<S, O, 7>), g, blk, 0, stream, b); break;          \
+    case 10: hipLaunchKernelGGL((batch_kernel<S, O, 10>), g, blk, 0, stream, b); break;        \
+    default: return hipErrorInvalidValue;                                                      \
+  }
+#define RFLBM_BATCH(S)            \
+  if (odd) {                      \
+    RFLBM_BATCH_R(S, true)        \
+  } else {                        \
+    RFLBM_BATCH_R(S, false)       \
+  }
+  switch (storage) {
+    case kF32: RFLBM_BATCH(kF32) break;
+    case kF16: RFLBM_BATCH(kF16) break;
+    case kBF16: RFLBM_BATCH(kBF16) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RFLBM_BATCH
+#undef RFLBM_BATCH_R
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_step(uint32_t* step, hipStream_t stream) {
+  hipLaunchKernelGGL(advance_step, dim3(1), dim3(64), 0, stream, step);
+  return hipGetLastError();
 }
 
 hipError_t launch_stats_reduce(const double* partials, uint32_t grid, double* scratch, double* acc,

@@ -98,3 +98,54 @@ def test_null_arguments():
     assert lib.rflbm_step(None, 1) == _binding.EINVAL
     assert lib.rflbm_step_count(None) == -1
     assert lib.rflbm_destroy(None) == _binding.OK
+
+
+def test_batch_validation():
+    lib = rf.load_library()
+    arr = (_binding.Params * 3)()
+    for i, d in enumerate([(8, 8, 8), (16, 4, 4), (5, 6, 7)]):
+        arr[i] = rf.make_params(d, kT=1e-5)
+    assert lib.rflbm_batch_required_bytes(3, arr) > 0
+    arr[1] = rf.make_params((16, 4, 4), kT=1e-5, storage="f16")
+    assert lib.rflbm_batch_required_bytes(3, arr) == 0  # mixed storage
+    arr[1] = rf.make_params((16, 4, 4), kT=1e-5, philox_rounds=7)
+    assert lib.rflbm_batch_required_bytes(3, arr) == 0  # mixed rounds
+    arr[1] = rf.make_params((16, 4, 4), tau=0.5)
+    assert lib.rflbm_batch_required_bytes(3, arr) == 0  # invalid replica
+    assert lib.rflbm_batch_required_bytes(0, arr) == 0
+    h = ctypes.c_void_p()
+    assert lib.rflbm_batch_create(3, arr, None, 0, None, ctypes.byref(h)) == _binding.EINVAL
+    assert b"replica 1" in lib.rflbm_last_error()
+
+
+def test_fast_division_is_exact(tmp_path):
+    """The magic-number division that maps a flattened node index to (x, y, z)
+    in the batched kernel, checked on the host against integer division."""
+    src = tmp_path / "fd.cpp"
+    csrc = os.path.join(os.path.dirname(_binding.__file__), "csrc", "fastdiv.hpp")
+    src.write_text(f"""
+#include "{csrc}"
+#include <cstdio>
+#include <random>
+int main() {{
+  std::mt19937_64 g(1); long bad = 0;
+  const uint32_t ds[] = {{2, 3, 5, 7, 31, 32, 33, 48, 64, 96, 97, 127, 128, 255, 256, 257, 1000,
+                          4095, 4096, 9216, 65535, 65536, 99991, 1u << 20, (1u << 31) - 1, 1u << 31,
+                          (1u << 31) + 1, 4294967295u}};
+  for (uint32_t d : ds) {{
+    const auto f = rflbm::make_fastdiv(d);
+    for (int k = 0; k < 200000; ++k) {{
+      uint32_t n = (uint32_t)g();
+      if (k < 1000) n = k;
+      else if (k < 2000) n = 0xffffffffu - (k - 1000);
+      if (rflbm::fast_div(n, f) != n / d) ++bad;
+    }}
+  }}
+  printf("%ld\\n", bad);
+  return bad != 0;
+}}
+""")
+    exe = tmp_path / "fd"
+    subprocess.run(["g++", "-O2", "-std=c++17", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "0"

@@ -1,0 +1,181 @@
+"""GPU tests of the batched form: many replicas stepped by one persistent launch.
+
+Replica r of a batch must evolve bit for bit like a stand-alone lattice with the
+same parameters (the same per-node update, only the launch differs), whatever
+the launch shape, with or without hipGraph replay; two replicas are also
+checked against the FP64 oracle over 100 steps.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rf():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_08820_amd as rf
+    return rf
+
+
+REPLICAS = [
+    dict(dims=(16, 16, 16), kT=1e-4, tau=0.8, tau_bulk=1.0, seed=1000, stream_id=0),
+    dict(dims=(17, 19, 23), kT=1e-5, tau=0.55, seed=1001, stream_id=1),
+    dict(dims=(32, 8, 12), kT=0.0, tau=1.2, seed=1002, stream_id=2),
+    dict(dims=(9, 40, 7), kT=3e-5, tau=0.7, model="bgk", seed=1003, stream_id=3),
+]
+
+
+def start_state(ora, dims, seed):
+    rho, u = wl.random_velocity(dims, seed)
+    f = ora.init_equilibrium(dims, rho, u)
+    w = ora.tables()["w"][:, None]
+    return f + 1e-3 * w * wl.normal_array(f.shape, seed + 7)
+
+
+def make_batch(rf, ora, storage="f32", **launch):
+    b = rf.Batch(REPLICAS, storage=storage)
+    for r, rep in enumerate(REPLICAS):
+        b[r].set_populations(start_state(ora, rep["dims"], 40 + r))
+    if launch:
+        b.set_launch(**launch)
+    return b
+
+
+def singles(rf, ora, storage="f32"):
+    out = []
+    for r, rep in enumerate(REPLICAS):
+        kw = {k: v for k, v in rep.items() if k != "dims"}
+        lat = rf.Lattice(rep["dims"], storage=storage, **kw)
+        lat.set_populations(start_state(ora, rep["dims"], 40 + r))
+        out.append(lat)
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("launch", [dict(tile=256, blocks_per_cu=0, graph_steps=0),
+                                    dict(tile=128, blocks_per_cu=2, graph_steps=4),
+                                    dict(tile=256, blocks_per_cu=8, graph_steps=6)])
+def test_replicas_equal_standalone_lattices(rf, ora, storage, launch):
+    print(f"[gpu] batch {storage} {launch}", flush=True)
+    if storage == "f16":
+        reps = [dict(r, kT=r["kT"] or 1e-5) for r in REPLICAS]
+    else:
+        reps = REPLICAS
+    b = rf.Batch(reps, storage=storage)
+    lats = []
+    for r, rep in enumerate(reps):
+        f = start_state(ora, rep["dims"], 40 + r)
+        b[r].set_populations(f)
+        kw = {k: v for k, v in rep.items() if k != "dims"}
+        lat = rf.Lattice(rep["dims"], storage=storage, **kw)
+        lat.set_populations(f)
+        lats.append(lat)
+    b.set_launch(**launch)
+    b.step(13)  # an odd count: graph replays from even t plus single steps
+    b.sync()
+    assert b.t == 13
+    for r, lat in enumerate(lats):
+        lat.step(13)
+        assert bool((b[r].populations() == lat.populations()).all()), r
+        assert b[r].t == 13
+
+
+def test_graph_replays_match_eager_steps(rf, ora):
+    """Graph replays interleaved with the program's own eager work and syncs:
+    every replay is checked against the same steps launched one by one."""
+    g = make_batch(rf, ora, tile=256, blocks_per_cu=4, graph_steps=4)
+    e = make_batch(rf, ora, tile=256, blocks_per_cu=4, graph_steps=0)
+    for rnd in range(5):
+        g.step(4)
+        e.step(4)
+        g.sync()
+        e.sync()
+        for r in range(len(REPLICAS)):
+            assert bool((g[r].populations() == e[r].populations()).all()), (rnd, r)
+        # eager work between replays: readback of moments on the same stream
+        _ = g[0].moments()
+
+
+def test_separate_launches_equal_persistent(rf, ora):
+    a = make_batch(rf, ora, tile=256, blocks_per_cu=8, graph_steps=2)
+    s = make_batch(rf, ora)
+    a.step(6)
+    s.step_separate(6)
+    s.sync()
+    assert s.t == 6
+    for r in range(len(REPLICAS)):
+        assert bool((a[r].populations() == s[r].populations()).all()), r
+
+
+def test_two_replicas_match_oracle(rf, ora):
+    b = make_batch(rf, ora, tile=128, blocks_per_cu=4, graph_steps=10)
+    refs = [start_state(ora, REPLICAS[r]["dims"], 40 + r) for r in (0, 1)]
+    params = []
+    for r in (0, 1):
+        rep = REPLICAS[r]
+        params.append(ora.make_params(kT=rep["kT"], tau_shear=rep["tau"],
+                                      tau_bulk=rep.get("tau_bulk"), seed=rep["seed"],
+                                      stream_id=rep["stream_id"]))
+    w = ora.tables()["w"][:, None]
+    for block in range(10):
+        b.step(10)
+        for r in (0, 1):
+            refs[r] = ora.run(params[r], REPLICAS[r]["dims"], refs[r], 10 * block, 10)
+            err = np.max(np.abs(b[r].populations().cpu().numpy() - refs[r]) / w)
+            assert err <= 1e-5, (block, r, err)
+
+
+def test_autotune_and_cache(rf, ora, tmp_path):
+    cache = tmp_path / "tune.txt"
+    b = make_batch(rf, ora)
+    lats = singles(rf, ora)
+    shape = b.autotune(trial_steps=4, cache_path=cache)
+    assert shape[0] in (128, 256)
+    assert cache.exists() and cache.read_text().strip()
+    t = b.t
+    for lat in lats:
+        lat.step(t)
+    b.step(4)
+    for r, lat in enumerate(lats):
+        lat.step(4)
+        assert bool((b[r].populations() == lat.populations()).all())
+    b2 = make_batch(rf, ora)
+    assert b2.autotune(trial_steps=4, cache_path=cache)[:2] == shape[:2]
+    assert b2.t == 0  # a cached choice takes no trial steps
+
+
+def test_views_refuse_own_stepping_and_checkpoint(rf, ora):
+    b = make_batch(rf, ora, graph_steps=2)
+    with pytest.raises(rf.RFLBMError) as e:
+        b[0].step(1)
+    assert e.value.status == -5
+    b.step(3)
+    snap = [b[r].populations() for r in range(len(REPLICAS))]
+    b.step(5)
+    end = [b[r].populations() for r in range(len(REPLICAS))]
+    c = make_batch(rf, ora, graph_steps=2)
+    c.t = 3
+    for r in range(len(REPLICAS)):
+        c[r].set_populations(snap[r])
+    c.step(5)
+    for r in range(len(REPLICAS)):
+        assert bool((c[r].populations() == end[r]).all()), r
+
+
+def test_batch_replica_table_workload(rf):
+    """The 64-replica table of the batched workload builds and steps."""
+    table = wl.replica_table(64, seed=5)
+    reps = [dict(dims=t["dims"], kT=t["kT"], tau=t["tau"], seed=t["seed"],
+                 stream_id=t["stream_id"]) for t in table]
+    b = rf.Batch(reps, storage="f32")
+    assert b.nodes == sum(int(np.prod(t["dims"])) for t in table)
+    b.set_launch(tile=256, blocks_per_cu=8, graph_steps=4)
+    b.step(8)
+    b.sync()
+    m = b[5].moments(rf.M_RHO).double().cpu().numpy()
+    assert abs(m.mean() - 1.0) < 1e-6

@@ -1,0 +1,133 @@
+"""Physics gates of the GPU path (Sec. II and III of the paper).
+
+- equipartition and a flat static structure factor: <u_a^2> = kT / rho0,
+  <d rho^2> = rho0 kT / cs2, <d Pi_aa^2> = mu b_4, <d Pi_ab^2> = mu b_7, each
+  within 1 %, and S(|n|) flat per shell (16^3, tau = 1, kT = 1e-4);
+- shear-wave decay at nu = cs2 (tau - 1/2) with thermal noise on (128^3,
+  tau_s = 0.8, tau_b = 1, kT = 1e-5);
+- storage precision: FP16 and BF16 deviation storage against FP32 and against
+  the FP64 oracle run with the same noise, kT in {1e-4, 1e-5, 1e-6}.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+CS2 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def rf():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_08820_amd as rf
+    return rf
+
+
+def er_from_stats(s, kT, rho0=1.0):
+    n = s["samples"] * s["nodes"]
+    var = lambda s1, s2: s2 / n - (s1 / n) ** 2
+    mu = rho0 * kT / CS2
+    return dict(
+        rho=var(s["sum_drho"], s["sum_drho2"]) / mu,
+        j=np.sum(var(s["sum_j"], s["sum_j2"])) / (3 * rho0 * kT),
+        u2=np.sum(s["sum_u2"] / n) / (3 * kT / rho0),
+        pi_d=np.sum(var(s["sum_pi"][:3], s["sum_pi2"][:3])) / (3 * mu * 2 / 9),
+        pi_o=np.sum(var(s["sum_pi"][3:], s["sum_pi2"][3:])) / (3 * mu / 9),
+    )
+
+
+def test_equipartition_and_flat_sk_16cube(rf):
+    dims, kT = (16, 16, 16), 1e-4
+    lat = rf.Lattice(dims, kT=kT, tau=1.0, seed=1)
+    lat.init_equilibrium()
+    lat.step(200)  # transient from the noise-free start
+    lat.stats_config(1)
+    for _ in range(80):
+        lat.step(10)
+        lat.sk_sample()
+    er = er_from_stats(lat.stats(), kT)
+    print(f"[gpu] 16^3 ER {er}", flush=True)
+    for k, v in er.items():
+        assert abs(v - 1) < 0.01, (k, v)
+    # flat S(|n|): shells 1..13 for rho and the summed momentum
+    sums, counts, samples = lat.sk("rho")
+    jsum = sum(lat.sk(f)[0] for f in ("jx", "jy", "jz"))
+    for field, s, theory in (("rho", sums, kT / CS2), ("j", jsum, 3 * kT)):
+        ratio = s[1:14] / counts[1:14] / samples / theory
+        sig = np.sqrt(2.0 / (counts[1:14] * (3 if field == "j" else 1) * samples / 4))
+        assert np.all(np.abs(ratio - 1) < np.maximum(0.02, 5 * sig)), (field, ratio)
+
+
+def test_shear_wave_decay_with_noise_128cube(rf):
+    dims = (128, 128, 128)
+    tau, L = 0.8, 128
+    lat = rf.Lattice(dims, kT=1e-5, tau=tau, tau_bulk=1.0, seed=2)
+    rho, u = wl.shear_wave(dims, amp=0.01)
+    lat.init_equilibrium(rho, u)
+    z = np.arange(L)
+    s = np.sin(2 * np.pi * z / L)
+    amps, ts = [], []
+    for k in range(51):
+        j = lat.moments(rf.M_RHO | rf.M_J).double().cpu().numpy()
+        ux = (j[1] / j[0]).reshape(L, L, L).mean(axis=(1, 2))
+        amps.append(2 * np.mean(ux * s))
+        ts.append(lat.t)
+        if k < 50:
+            lat.step(100)
+    rate = -np.polyfit(ts[5:], np.log(amps[5:]), 1)[0]
+    nu_k2 = CS2 * (tau - 0.5) * (2 * np.pi / L) ** 2
+    print(f"[gpu] shear decay rate {rate:.6e} vs nu k^2 {nu_k2:.6e}; "
+          f"A(5000)/A(0) = {amps[-1] / amps[0]:.4f}", flush=True)
+    assert abs(rate / nu_k2 - 1) < 0.005
+    assert abs(amps[-1] / amps[0] - np.exp(-nu_k2 * 5000)) < 0.005
+    lat.sync()
+
+
+def thermal_er(rf, ora, storage, kT, dims=(32, 32, 32), steps=400, burn=100, oracle=False):
+    kw = dict(kT=kT, tau=0.6, tau_bulk=1.0, seed=11)
+    lat = rf.Lattice(dims, storage=storage, **kw)
+    lat.init_equilibrium()
+    lat.step(burn)
+    lat.stats_config(2)
+    lat.step(steps)
+    er = er_from_stats(lat.stats(), kT)
+    if not oracle:
+        return er, None
+    p = ora.make_params(kT=kT, tau_shear=0.6, tau_bulk=1.0, seed=11)
+    w = ora.tables()["w"]
+    f = np.tile(w[:, None], (1, int(np.prod(dims))))
+    f = ora.run(p, dims, f, 0, burn)
+    acc = dict(rho=0.0, u2=0.0)
+    n = 0
+    for t in range(burn, burn + steps):
+        if (t - burn) % 2 == 0:
+            m = ora.moments(f)
+            acc["rho"] += np.var(m["rho"])
+            acc["u2"] += np.mean((m["j"] / m["rho"]) ** 2) * 3
+            n += 1
+        f = ora.step(p, dims, f, t)
+    ora_er = dict(rho=acc["rho"] / n / (kT / CS2), u2=acc["u2"] / n / (3 * kT))
+    return er, ora_er
+
+
+@pytest.mark.parametrize("kT", [1e-4, 1e-5, 1e-6])
+def test_storage_precision_equipartition(rf, ora, kT):
+    """Same seed, same noise: the FP32, FP16 and BF16 runs and the FP64 oracle
+    follow the same trajectory up to rounding, so differences in <u^2> measure
+    the storage precision alone; each must also be within 1 % of theory."""
+    er32, er64 = thermal_er(rf, ora, "f32", kT, oracle=True)
+    er16, _ = thermal_er(rf, ora, "f16", kT)
+    erbf, _ = thermal_er(rf, ora, "bf16", kT)
+    print(f"[gpu] kT={kT}: ER(u2) oracle {er64['u2']:.5f} f32 {er32['u2']:.5f} "
+          f"f16 {er16['u2']:.5f} bf16 {erbf['u2']:.5f}; ER(rho) oracle {er64['rho']:.5f} "
+          f"f32 {er32['rho']:.5f} f16 {er16['rho']:.5f} bf16 {erbf['rho']:.5f}", flush=True)
+    assert abs(er32["u2"] - er64["u2"]) < 1e-4
+    assert abs(er16["u2"] - er64["u2"]) < 2e-3
+    for er in (er32, er16, erbf):
+        assert abs(er["u2"] - 1) < 0.01
+        assert abs(er["rho"] - 1) < 0.02
+    assert abs(erbf["u2"] - er32["u2"]) < 0.01
