@@ -127,6 +127,15 @@ rflbm_status rflbm_get_params(const rflbm_lattice* lat, rflbm_params* p);
 rflbm_status rflbm_init_equilibrium(rflbm_lattice* lat, const double* rho, const double* u,
                                     int host_ptrs);
 
+/* Thermalised start: f_i = f^(0)_i(rho, u) + sqrt(rho0 kT w_i / cs^2) xi_i,
+ * the stationary covariance of the fluctuating update in the linear regime
+ * (Eq. fluct_phi), so that statistics need no equilibration transient.  xi_i
+ * is normal i of the node's Philox/Box-Muller stream at the reserved step word
+ * 0xFFFFFFFF (calls j = 0..6; 27 of 28 normals used), keyed like the step's
+ * noise.  Arguments as for rflbm_init_equilibrium. */
+rflbm_status rflbm_init_thermal(rflbm_lattice* lat, const double* rho, const double* u,
+                                int host_ptrs);
+
 /* Advances nsteps >= 0 time steps (one fused stream-and-collide kernel per
  * step, Eq. r-flbe2).  Asynchronous on the lattice stream.  Instability is
  * reported by the next rflbm_sync. */
@@ -146,6 +155,11 @@ rflbm_status rflbm_set_step_count(rflbm_lattice* lat, int64_t t);
 /* Reads the populations f(x, t) (FP64, planar, 27 N values) into dst.  With a
  * host dst the call waits for the stream. */
 rflbm_status rflbm_get_populations(rflbm_lattice* lat, double* dst, int dst_is_host);
+/* Reads f(x, t) at `count` nodes only: nodes[k] (device array of node indices
+ * n < N) -> dst[i * count + k] (device, FP64, 27 * count values).  For
+ * checking large boxes against a reference one node at a time. */
+rflbm_status rflbm_get_populations_at(rflbm_lattice* lat, const uint32_t* nodes, uint32_t count,
+                                      double* dst);
 /* Writes the populations f(x, t) from src (FP64, planar, 27 N values); clears
  * the instability flag. */
 rflbm_status rflbm_set_populations(rflbm_lattice* lat, const double* src, int src_is_host);

@@ -105,6 +105,9 @@ def _load():
     lib.ora_init_equilibrium.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp,
                                          dp]
     lib.ora_init_equilibrium.restype = ctypes.c_int
+    lib.ora_init_thermal.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, dp, dp, dp]
+    lib.ora_init_thermal.restype = ctypes.c_int
     lib.ora_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -188,6 +191,20 @@ def init_equilibrium(dims, rho, u) -> np.ndarray:
     uu = np.ascontiguousarray(np.reshape(u, (3, n)), dtype=np.float64)
     f = np.zeros((27, n))
     lib.ora_init_equilibrium(nx, ny, nz, _dp(rr), _dp(uu), _dp(f))
+    return f
+
+
+def init_thermal(params: Params, dims, rho=None, u=None) -> np.ndarray:
+    """f^(0)(rho, u) plus Gaussian populations of covariance rho0 kT w_i / cs2
+    (Philox at the reserved step word 0xFFFFFFFF)."""
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    lib = _load()
+    rr = None if rho is None else np.ascontiguousarray(np.broadcast_to(rho, (n,)), dtype=np.float64)
+    uu = None if u is None else np.ascontiguousarray(np.reshape(u, (3, n)), dtype=np.float64)
+    f = np.zeros((27, n))
+    lib.ora_init_thermal(ctypes.byref(params), nx, ny, nz, None if rr is None else _dp(rr),
+                         None if uu is None else _dp(uu), _dp(f))
     return f
 
 

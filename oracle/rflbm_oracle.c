@@ -26,7 +26,9 @@
  *   - the post-collision population of Eq. r-flbe2 (Reg-FLBM) or Eq. flbe
  *     (BGK-FLBM comparator, equilibrium from Eq. hermite_feq2 as in Sec. III);
  *   - push streaming f_i(x + c_i, t + 1) = f*_i(x, t) (Eq. eq:streaming) on a
- *     periodic box.
+ *     periodic box;
+ *   - an optional thermalised start drawn from the stationary covariance
+ *     rho0 kT w_i / c_s^2 (ora_init_thermal).
  *
  * Readings where the paper is silent (they are listed with their reasons in the
  * design notes of the repository):
@@ -435,6 +437,40 @@ int ora_run(const ora_params* p, int32_t nx, int32_t ny, int32_t nz, uint32_t st
     double* t = a; a = b; b = t;
   }
   if (a != f) memcpy(f, a, (size_t)total * sizeof(double));
+  return 0;
+}
+
+/* Thermalised start: f_i = f^(0)_i(rho, u) + sqrt(mu w_i) xi_i with
+ * mu = rho0 kT / c_s^2, the stationary covariance mu w_i delta_ij that the
+ * fluctuation-dissipation balance of Eq. fluct_phi sustains in the linear
+ * regime.  xi_i is the i-th normal of the node's Box-Muller stream drawn at the
+ * reserved step word 0xFFFFFFFF with calls j = 0..6 (28 normals, 27 used):
+ * word w of call j gives uniform 4j + w as in ora_uniforms. */
+int ora_init_thermal(const ora_params* p, int32_t nx, int32_t ny, int32_t nz, const double* rho,
+                     const double* u, double* f) {
+  build_tables();
+  const int64_t N = (int64_t)nx * ny * nz;
+  const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+  const double mu = p->rho0 * p->kT / CS2;
+#pragma omp parallel for schedule(static)
+  for (int64_t n = 0; n < N; ++n) {
+    double fe[NPOP], uni[28], z[28];
+    const double un[3] = {u ? u[n] : 0.0, u ? u[N + n] : 0.0, u ? u[2 * N + n] : 0.0};
+    ora_equilibrium(rho ? rho[n] : p->rho0, un, fe);
+    for (uint32_t j = 0; j < 7; ++j) {
+      const uint32_t ctr[4] = {(uint32_t)n, 0xFFFFFFFFu, j, p->stream_id};
+      uint32_t words[4];
+      ora_philox4x32(ctr, key, p->rounds, words);
+      for (int w = 0; w < 4; ++w) uni[4 * j + w] = ((double)(words[w] >> 8) + 1.0) / 16777216.0;
+    }
+    for (int q = 0; q < 14; ++q) {
+      const double radius = sqrt(-2.0 * log(uni[2 * q]));
+      const double theta = 2.0 * 3.14159265358979323846 * uni[2 * q + 1];
+      z[2 * q] = radius * cos(theta);
+      z[2 * q + 1] = radius * sin(theta);
+    }
+    for (int i = 0; i < NPOP; ++i) f[i * N + n] = fe[i] + sqrt(mu * W[i]) * z[i];
+  }
   return 0;
 }
 

@@ -75,12 +75,14 @@ _SIGS = {
     "rflbm_set_params": (ctypes.c_int, [_VP, _PP]),
     "rflbm_get_params": (ctypes.c_int, [_VP, _PP]),
     "rflbm_init_equilibrium": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
+    "rflbm_init_thermal": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
     "rflbm_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
     "rflbm_sync": (ctypes.c_int, [_VP]),
     "rflbm_step_count": (ctypes.c_int64, [_VP]),
     "rflbm_set_step_count": (ctypes.c_int, [_VP, ctypes.c_int64]),
     "rflbm_get_populations": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     "rflbm_set_populations": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
+    "rflbm_get_populations_at": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP]),
     "rflbm_get_moments": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, ctypes.c_int]),
     "rflbm_stats_config": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "rflbm_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(Stats)]),
@@ -262,11 +264,36 @@ class Lattice:
         self._keep = (r, v)  # alive until the stream has consumed them
         self.stream.synchronize()
 
+    def init_thermal(self, rho=None, u=None):
+        """f^(0)(rho, u) plus Gaussian deviations of the stationary covariance."""
+        r = None if rho is None else _as_device_f64(np.broadcast_to(rho, (self.n,))
+                                                     if not hasattr(rho, "data_ptr") else rho,
+                                                     self.device)
+        v = None if u is None else _as_device_f64(u, self.device).reshape(3, self.n)
+        check(self.lib.rflbm_init_thermal(self._h, None if r is None else _VP(_dev_ptr(r)),
+                                          None if v is None else _VP(_dev_ptr(v)), 0))
+        self._keep = (r, v)
+        self.stream.synchronize()
+
     def populations(self):
         """f(x, t) as a (27, N) float64 tensor on the device."""
         torch = _torch()
         out = torch.empty((27, self.n), dtype=torch.float64, device=self.device)
         check(self.lib.rflbm_get_populations(self._h, _VP(_dev_ptr(out)), 0))
+        return out
+
+    def populations_at(self, nodes):
+        """f(x, t) at the given node indices as a (27, len(nodes)) float64 tensor
+        on the device (indices are checked against the box on the host)."""
+        torch = _torch()
+        idx = np.ascontiguousarray(nodes, dtype=np.int64)
+        if idx.size and (idx.min() < 0 or idx.max() >= self.n):
+            raise ValueError("node index outside the box")
+        nd = torch.as_tensor(idx.astype(np.uint32), device=self.device)
+        out = torch.empty((27, idx.size), dtype=torch.float64, device=self.device)
+        check(self.lib.rflbm_get_populations_at(self._h, _VP(_dev_ptr(nd)), int(idx.size),
+                                                _VP(_dev_ptr(out))))
+        self.stream.synchronize()
         return out
 
     def set_populations(self, f):

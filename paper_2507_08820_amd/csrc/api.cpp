@@ -384,6 +384,21 @@ rflbm_status rflbm_init_equilibrium(rflbm_lattice* L, const double* rho, const d
 
 
 
+rflbm_status rflbm_init_thermal(rflbm_lattice* L, const double* rho, const double* u, int host_ptrs) {
+  if (rflbm_status s = check_lattice(L)) return s;
+  const uint64_t N = nodes(L);
+  DeviceIn drho, du;
+  if (rflbm_status s = stage_in(rho, N * sizeof(double), host_ptrs, L->stream, drho)) return s;
+  if (rflbm_status s = stage_in(u, 3 * N * sizeof(double), host_ptrs, L->stream, du)) return s;
+  RFLBM_HIP(launch_init_thermal(L->p.storage, gather_args(L, L->p, L->t), static_cast<const double*>(drho.ptr),
+                                static_cast<const double*>(du.ptr), static_cast<uint32_t>(L->p.seed & 0xffffffffu),
+                                static_cast<uint32_t>(L->p.seed >> 32), L->p.stream_id,
+                                static_cast<int>(L->p.philox_rounds), L->p.kT, L->stream));
+  if (rflbm_status s = clear_flag(L)) return s;
+  if (host_ptrs) RFLBM_HIP(hipStreamSynchronize(L->stream));
+  return RFLBM_OK;
+}
+
 rflbm_status rflbm_step(rflbm_lattice* L, int64_t nsteps) {
   if (rflbm_status s = check_lattice(L)) return s;
   if (L->is_view) return fail(RFLBM_ESTATE, "replicas of a batch are stepped with rflbm_batch_step");
@@ -425,6 +440,13 @@ rflbm_status rflbm_get_populations(rflbm_lattice* L, double* dst, int dst_is_hos
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("get_populations: ") + hipGetErrorString(e));
+  return RFLBM_OK;
+}
+
+rflbm_status rflbm_get_populations_at(rflbm_lattice* L, const uint32_t* nodes, uint32_t count, double* dst) {
+  if (rflbm_status s = check_lattice(L)) return s;
+  if (count > 0 && (!nodes || !dst)) return fail(RFLBM_EINVAL, "nodes and dst must be device arrays");
+  RFLBM_HIP(launch_get_populations_at(L->p.storage, gather_args(L, L->p, L->t), nodes, count, dst, L->stream));
   return RFLBM_OK;
 }
 

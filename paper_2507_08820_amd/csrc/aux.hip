@@ -57,6 +57,22 @@ __global__ void get_pop_kernel(const GatherArgs g, double* dst) {
 }
 
 template <int S>
+__global__ void get_pop_at_kernel(const GatherArgs g, const uint32_t* nodes, uint32_t count, double* dst) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const T* pop = static_cast<const T*>(g.pop);
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const NodeXYZ p = coords(nodes[k], g.nx, g.ny);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int cls = speed_class(i);
+    const float d = C::decode(pop[slot_index(i, p, g)], g.sigma[cls]);
+    dst[static_cast<uint64_t>(i) * count + k] = class_weight(cls) * g.rho0 + static_cast<double>(d);
+  }
+}
+
+template <int S>
 __global__ void set_pop_kernel(const GatherArgs g, const double* src) {
   using C = Codec<S>;
   using T = typename C::T;
@@ -101,6 +117,58 @@ __global__ void init_eq_kernel(const GatherArgs g, const double* rho, const doub
       const int cls = speed_class(i);
       const double feq = r * fac[0][i % 3] * fac[1][(i / 3) % 3] * fac[2][i / 9];
       const double d = feq - class_weight(cls) * g.rho0;
+      pop[slot_index(i, p, g)] = C::encode(static_cast<float>(d), g.inv_sigma[cls]);
+    }
+  }
+}
+
+// Thermalised start: f_i = f^(0)_i(rho, u) + sqrt(rho0 kT w_i / cs2) xi_i, the
+// stationary covariance of the fluctuating update (Eq. fluct_phi) in the
+// linear regime.  xi_i is normal i of the node's Box-Muller stream at the
+// reserved step word 0xFFFFFFFF, Philox calls j = 0..6 (28 normals, 27 used);
+// set-up code, so the transform runs in FP64.
+template <int S, int R>
+__global__ void init_thermal_kernel(const GatherArgs g, const double* rho, const double* u, uint32_t key0,
+                                    uint32_t key1, uint32_t sid, double kT) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  T* pop = static_cast<T*>(const_cast<void*>(g.pop));
+  const double mu = g.rho0 * kT * 3.0;
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+    const double r = rho ? rho[n] : g.rho0;
+    const double ua[3] = {u ? u[n] : 0.0, u ? u[N + n] : 0.0, u ? u[2 * N + n] : 0.0};
+    double fac[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double uu = ua[a] * ua[a];
+      fac[a][0] = (1.0 / 6.0) * (1.0 - 3.0 * ua[a] + 3.0 * uu);
+      fac[a][1] = (2.0 / 3.0) * (1.0 - 1.5 * uu);
+      fac[a][2] = (1.0 / 6.0) * (1.0 + 3.0 * ua[a] + 3.0 * uu);
+    }
+    double z[28];
+#pragma unroll
+    for (uint32_t j = 0; j < 7; ++j) {
+      const Word4 w = philox<R>(Word4{static_cast<uint32_t>(n), 0xFFFFFFFFu, j, sid}, key0, key1);
+      const double u0 = (static_cast<double>(w.w0 >> 8) + 1.0) * 0x1p-24;
+      const double u1 = (static_cast<double>(w.w1 >> 8) + 1.0) * 0x1p-24;
+      const double u2 = (static_cast<double>(w.w2 >> 8) + 1.0) * 0x1p-24;
+      const double u3 = (static_cast<double>(w.w3 >> 8) + 1.0) * 0x1p-24;
+      const double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
+      const double two_pi = 6.283185307179586476925;
+      z[4 * j + 0] = ra * cos(two_pi * u1);
+      z[4 * j + 1] = ra * sin(two_pi * u1);
+      z[4 * j + 2] = rb * cos(two_pi * u3);
+      z[4 * j + 3] = rb * sin(two_pi * u3);
+    }
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int cls = speed_class(i);
+      const double w = class_weight(cls);
+      const double feq = r * fac[0][i % 3] * fac[1][(i / 3) % 3] * fac[2][i / 9];
+      const double d = feq - w * g.rho0 + sqrt(mu * w) * z[i];
       pop[slot_index(i, p, g)] = C::encode(static_cast<float>(d), g.inv_sigma[cls]);
     }
   }
@@ -235,6 +303,13 @@ hipError_t launch_get_populations(int storage, const GatherArgs& g, double* dst,
   return hipGetLastError();
 }
 
+hipError_t launch_get_populations_at(int storage, const GatherArgs& g, const uint32_t* nodes, uint32_t count,
+                                     double* dst, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  RFLBM_DISPATCH_STORAGE(storage, get_pop_at_kernel, dim3((count + 255) / 256), dim3(256), s, g, nodes, count, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_populations(int storage, const GatherArgs& g, const double* src, hipStream_t s) {
   const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
   RFLBM_DISPATCH_STORAGE(storage, set_pop_kernel, dim3(grid_for(N, 256)), dim3(256), s, g, src);
@@ -245,6 +320,29 @@ hipError_t launch_init_equilibrium(int storage, const GatherArgs& g, const doubl
                                    const double* u, hipStream_t s) {
   const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
   RFLBM_DISPATCH_STORAGE(storage, init_eq_kernel, dim3(grid_for(N, 256)), dim3(256), s, g, rho, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_thermal(int storage, const GatherArgs& g, const double* rho, const double* u,
+                               uint32_t key0, uint32_t key1, uint32_t sid, int rounds, double kT,
+                               hipStream_t s) {
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  const dim3 grid(grid_for(N, 256)), block(256);
+#define RFLBM_THERMAL(R)                                                                             \
+  switch (storage) {                                                                                 \
+    case kF32: hipLaunchKernelGGL((init_thermal_kernel<kF32, R>), grid, block, 0, s, g, rho, u, key0, key1, sid, kT); break;   \
+    case kF16: hipLaunchKernelGGL((init_thermal_kernel<kF16, R>), grid, block, 0, s, g, rho, u, key0, key1, sid, kT); break;   \
+    case kBF16: hipLaunchKernelGGL((init_thermal_kernel<kBF16, R>), grid, block, 0, s, g, rho, u, key0, key1, sid, kT); break; \
+    default: return hipErrorInvalidValue;                                                            \
+  }
+  if (rounds == 10) {
+    RFLBM_THERMAL(10)
+  } else if (rounds == 7) {
+    RFLBM_THERMAL(7)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef RFLBM_THERMAL
   return hipGetLastError();
 }
 

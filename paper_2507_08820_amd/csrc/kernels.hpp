@@ -104,12 +104,20 @@ struct GatherArgs {
 
 // f(x, t) -> dst[i * N + n] (FP64, absolute populations).
 hipError_t launch_get_populations(int storage, const GatherArgs& g, double* dst, hipStream_t s);
+// f(x, t) at nodes[0..count) -> dst[i * count + k] (FP64, absolute); the
+// node indices must be < nx ny nz.
+hipError_t launch_get_populations_at(int storage, const GatherArgs& g, const uint32_t* nodes,
+                                     uint32_t count, double* dst, hipStream_t s);
 // src[i * N + n] (FP64, absolute) -> storage slots for step parity g.odd.
 hipError_t launch_set_populations(int storage, const GatherArgs& g, const double* src,
                                   hipStream_t s);
 // Equilibrium f^(0)(rho, u) (rho, u may be null) -> storage slots.
 hipError_t launch_init_equilibrium(int storage, const GatherArgs& g, const double* rho,
                                    const double* u, hipStream_t s);
+// f^(0)(rho, u) plus Gaussian deviations of covariance rho0 kT w_i / cs2.
+hipError_t launch_init_thermal(int storage, const GatherArgs& g, const double* rho, const double* u,
+                               uint32_t key0, uint32_t key1, uint32_t sid, int rounds, double kT,
+                               hipStream_t s);
 // Moment fields (FP32, planar) selected by mask (1 rho, 2 j, 4 Pi).
 hipError_t launch_get_moments(int storage, const GatherArgs& g, uint32_t mask, float* dst,
                               hipStream_t s);

@@ -31,6 +31,16 @@ struct Word4 {
   uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ c: one gfx950 three-input bitwise instruction (truth table 0x96)
+// instead of two exclusive-ors.
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+  return a ^ b ^ c;
+#endif
+}
+
 // R rounds of Philox4x32 on counter c with key (k0, k1).
 template <int R>
 __host__ __device__ __forceinline__ Word4 philox(Word4 c, uint32_t k0, uint32_t k1) {
@@ -39,9 +49,9 @@ __host__ __device__ __forceinline__ Word4 philox(Word4 c, uint32_t k0, uint32_t 
     const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * c.w0;
     const uint64_t p2 = static_cast<uint64_t>(kPhiloxM1) * c.w2;
     Word4 n;
-    n.w0 = static_cast<uint32_t>(p2 >> 32) ^ c.w1 ^ k0;
+    n.w0 = xor3(static_cast<uint32_t>(p2 >> 32), c.w1, k0);
     n.w1 = static_cast<uint32_t>(p2);
-    n.w2 = static_cast<uint32_t>(p0 >> 32) ^ c.w3 ^ k1;
+    n.w2 = xor3(static_cast<uint32_t>(p0 >> 32), c.w3, k1);
     n.w3 = static_cast<uint32_t>(p0);
     c = n;
     k0 += kPhiloxW0;

@@ -1,0 +1,149 @@
+"""Parity at full size, on sampled nodes, in the launch configuration the
+benchmark times.
+
+For a sample of nodes y the test reads f(t) at the 27 source nodes y - c_i,
+lets the oracle collide each source node with its own Philox noise (node
+index, step t), and compares population i of that post-collision state with
+what the GPU stored at y after the step, f_i(y, t + 1) = f*_i(y - c_i, t)
+(Eq. eq:streaming).  Two consecutive steps cover both AA parities.  Boxes:
+the 512^3 benchmark workload (FP32 and FP16 storage), the largest FP32 box the
+library accepts (1024^3, 116 GB), and two replicas of the 64-replica batch.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rf():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_08820_amd as rf
+    return rf
+
+
+def sample_nodes(dims, count, seed):
+    nx, ny, nz = dims
+    g = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (0, ny - 1, 0), (nx - 1, 0, nz // 2),
+           (nx // 2, ny // 2, 0), (1, ny - 1, nz - 1)]
+    pts += [tuple(int(v) for v in g.integers(0, (nx, ny, nz))) for _ in range(count - len(pts))]
+    return np.array(pts, dtype=np.int64)
+
+
+def source_nodes(pts, dims):
+    """(S, 27) node indices of y - c_i, periodic."""
+    nx, ny, nz = dims
+    i = np.arange(27)
+    c = np.stack([i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1], axis=1)
+    src = (pts[:, None, :] - c[None, :, :]) % np.array([nx, ny, nz])
+    return src[..., 0] + nx * (src[..., 1] + ny * src[..., 2])
+
+
+def ulp16(q, storage):
+    mant, emin = (10, -14) if storage == "f16" else (7, -126)
+    e = np.floor(np.log2(np.maximum(np.abs(q), 2.0 ** emin)))
+    return 2.0 ** (np.maximum(e, emin) - mant)
+
+
+def check_one_step(lat, ora, p, dims, pts, storage="f32", sigma=None):
+    t = lat.t
+    src = source_nodes(pts, dims)
+    fsrc = lat.populations_at(src.ravel()).cpu().numpy().reshape(27, len(pts), 27)
+    lat.step(1)
+    got = lat.populations_at(pts[:, 0] + dims[0] * (pts[:, 1] + dims[1] * pts[:, 2])).cpu().numpy()
+    w = ora.tables()["w"]
+    want = np.empty_like(got)
+    noisy = p.kT > 0
+    for k in range(len(pts)):
+        for i in range(27):
+            node = int(src[k, i])
+            r = ora.normals(p.seed, p.stream_id, p.rounds, node, t)[:23] if noisy else np.zeros(23)
+            want[i, k] = ora.collide(p, fsrc[:, k, i], r)[i]
+    if storage == "f32":
+        err = np.max(np.abs(got - want) / w[:, None])
+        assert err <= TOL, (t, err)
+        return err
+    q_ref = (want - w[:, None]) / sigma[:, None]
+    q_got = (got - w[:, None]) / sigma[:, None]
+    allowed = 0.5 * ulp16(q_ref, storage) * 1.001 + 2e-6 * (1 + np.abs(q_ref))
+    assert np.all(np.abs(q_got - q_ref) <= allowed), t
+    return float(np.max(np.abs(q_got - q_ref) / allowed))
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_bench_workload_512cube_sampled(rf, ora, storage):
+    dims = (512, 512, 512)
+    print(f"[gpu] full size {dims} {storage}", flush=True)
+    lat = rf.Lattice(dims, storage=storage, kT=1e-5, tau=0.6, tau_bulk=0.6, tau_ghost=1.0, seed=3)
+    assert lat.get_launch() == (256, True)  # the configuration bench.py times
+    rho, u = wl.taylor_green_device(dims, amp=0.01, device=lat.device)
+    lat.init_equilibrium(rho, u)
+    del rho, u
+    lat.step(3)  # leave the noise-free start; next steps are odd then even
+    p = ora.make_params(kT=1e-5, tau_shear=0.6, tau_bulk=0.6, seed=3)
+    pts = sample_nodes(dims, 192, seed=17)
+    sigma = np.sqrt(ora.tables()["w"] * 1e-5 * 3.0)
+    for _ in range(2):
+        check_one_step(lat, ora, p, dims, pts, storage, sigma)
+    lat.sync()
+    lat.close()
+
+
+def test_largest_fp32_box_sampled(rf, ora):
+    dims = (1024, 1024, 1024)
+    print(f"[gpu] largest box {dims}", flush=True)
+    lat = rf.Lattice(dims, kT=1e-4, tau=0.7, seed=5)
+    lat.init_equilibrium()
+    p = ora.make_params(kT=1e-4, tau_shear=0.7, seed=5)
+    pts = sample_nodes(dims, 96, seed=23)
+    for _ in range(2):
+        check_one_step(lat, ora, p, dims, pts)
+    lat.sync()
+    lat.close()
+
+
+def test_batch_workload_sampled(rf, ora):
+    table = wl.replica_table(64, seed=5)
+    reps = [dict(dims=t["dims"], kT=t["kT"], tau=t["tau"], seed=t["seed"], stream_id=t["stream_id"])
+            for t in table]
+    b = rf.Batch(reps, storage="f32")
+    for r, t in enumerate(table):
+        rho, u = wl.taylor_green_device(t["dims"], amp=0.01, device=b.device)
+        b[r].init_equilibrium(rho, u)
+    b.set_launch(256, 8, 20)
+    b.step(21)
+    for r in (0, 37):
+        rep = table[r]
+        p = ora.make_params(kT=rep["kT"], tau_shear=rep["tau"], seed=rep["seed"],
+                            stream_id=rep["stream_id"])
+        pts = sample_nodes(rep["dims"], 64, seed=r)
+        view = b[r]
+        t = view.t
+        src = source_nodes(pts, rep["dims"])
+        fsrc = view.populations_at(src.ravel()).cpu().numpy().reshape(27, len(pts), 27)
+        b.step(1)
+        nx, ny, _ = rep["dims"]
+        got = view.populations_at(pts[:, 0] + nx * (pts[:, 1] + ny * pts[:, 2])).cpu().numpy()
+        w = ora.tables()["w"]
+        for k in range(len(pts)):
+            for i in range(27):
+                node = int(src[k, i])
+                r_ = ora.normals(p.seed, p.stream_id, p.rounds, node, t)[:23]
+                want = ora.collide(p, fsrc[:, k, i], r_)[i]
+                assert abs(got[i, k] - want) / w[i] <= TOL, (r, k, i)
+    b.sync()
+    b.close()
+
+
+def test_zero_steps_is_a_no_op(rf, ora):
+    lat = rf.Lattice((8, 8, 8), kT=1e-4)
+    before = lat.populations()
+    lat.step(0)
+    assert lat.t == 0 and bool((lat.populations() == before).all())

@@ -281,3 +281,22 @@ def test_set_params_keeps_state(rf, ora):
         after = lat.populations().cpu().numpy()
         tol = 1e-7 if storage == "f32" else 3e-3 * np.sqrt(2e-4 * 3 * 1.3)
         assert np.max(np.abs(after - before)) < tol
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_thermal_start_matches_oracle(rf, ora, storage):
+    dims = (17, 19, 23)
+    kw = dict(kT=1e-4, tau=0.8, seed=(3 << 32) + 5, stream_id=4, rho0=1.2)
+    rho, u = wl.random_velocity(dims, seed=33, rho0=1.2)
+    lat = rf.Lattice(dims, storage=storage, **kw)
+    lat.init_thermal(rho, u)
+    want = ora.init_thermal(oracle_params(ora, kw), dims, rho, u)
+    got = lat.populations().cpu().numpy()
+    w = weights(ora)[:, None]
+    if storage == "f32":
+        assert np.max(np.abs(got - want) / (1.2 * w)) < 1e-6
+    else:
+        sigma = np.sqrt(1.2 * 1e-4 * 3 * w)
+        q_want, q_got = (want - 1.2 * w) / sigma, (got - 1.2 * w) / sigma
+        allowed = 0.5 * ulp16(q_want, storage) * 1.001 + 2e-6 * (1 + np.abs(q_want))
+        assert np.all(np.abs(q_got - q_want) <= allowed)

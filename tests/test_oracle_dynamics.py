@@ -154,3 +154,35 @@ def test_streaming_moves_population_along_its_velocity(ora):
         assert abs(g[i, d] - 1.01 * w[i]) < 1e-15
         others = np.delete(g[i], d)
         np.testing.assert_allclose(others, w[i], rtol=0, atol=1e-15)
+
+
+def test_thermal_start_has_stationary_covariance(ora):
+    """The thermalised start has mean f^(0) and covariance rho0 kT w_i / cs2
+    per population, independent across populations and nodes."""
+    dims = (24, 24, 24)
+    kT, rho0 = 1e-4, 1.3
+    p = ora.make_params(kT=kT, rho0=rho0, seed=9, stream_id=2)
+    f = ora.init_thermal(p, dims)
+    w = ora.tables()["w"]
+    n = f.shape[1]
+    d = f - rho0 * w[:, None]
+    np.testing.assert_allclose(d.mean(axis=1) / np.sqrt(rho0 * kT / CS2 * w), 0, atol=5 / np.sqrt(n))
+    var = d.var(axis=1) / (rho0 * kT / CS2 * w)
+    np.testing.assert_allclose(var, 1, atol=5 * np.sqrt(2 / n))
+    cc = np.corrcoef(d / np.sqrt(w)[:, None])
+    assert np.abs(cc - np.eye(27)).max() < 5 / np.sqrt(n)
+    # a different seed or stream gives a different draw
+    q = ora.make_params(kT=kT, rho0=rho0, seed=9, stream_id=3)
+    assert not np.array_equal(ora.init_thermal(q, dims), f)
+
+
+def test_thermal_start_stays_thermal(ora):
+    """Started from the stationary covariance, the equipartition ratios hold
+    from the first step on (no transient)."""
+    dims = (16, 16, 16)
+    kT = 1e-4
+    p = ora.make_params(kT=kT, tau_shear=0.6, tau_bulk=1.0, seed=4)
+    f = ora.init_thermal(p, dims)
+    mean, _ = sample_run(ora, dims, p, f, steps=60, every=2, sk_every=1000)
+    np.testing.assert_allclose(mean["u2"] / kT, 1.0, atol=0.02)
+    np.testing.assert_allclose(mean["rho"] / (kT / CS2), 1.0, atol=0.02)
