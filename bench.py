@@ -138,6 +138,60 @@ def run_batch(storage, steps=200, graph_steps=20):
     return out
 
 
+def table3_run(dims=(256, 256, 256), taus=(0.5001, 0.51, 1.0, 10.0, 100.0),
+               bgk_taus=(0.51, 1.0, 50.0), kT=1.0 / 3000.0, burn=2000, steps=20000, every=50,
+               sk_every=500):
+    """Equilibration ratios of Sec. III (Table III) and the |k|-resolved ratio of
+    the total momentum (Fig. 2: min and max over 4 <= |k| <= 64) on a periodic
+    box at rest, rho0 = 1, kT = 1/3000, thermalised start, ghosts at tau = 1."""
+    import numpy as np
+    import torch
+
+    import paper_2507_08820_amd as rf
+
+    cs2 = 1.0 / 3.0
+    mu = kT / cs2
+    rows = []
+    for model, tlist in (("reg", taus), ("bgk", bgk_taus)):
+        for tau in tlist:
+            lat = rf.Lattice(dims, kT=kT, tau=tau, tau_bulk=tau, tau_ghost=1.0, model=model, seed=7)
+            lat.init_thermal()
+            lat.step(burn)
+            lat.stats_config(every)
+            lat.reset_stats()
+            for _ in range(steps // sk_every):
+                lat.step(sk_every)
+                lat.sk_sample()
+            try:
+                lat.sync()
+                stable = True
+            except rf.RFLBMError:
+                stable = False
+            s = lat.stats()
+            n = s["samples"] * s["nodes"]
+            var = lambda a, b: b / n - (a / n) ** 2
+            row = {"model": model, "tau": tau, "stable": stable, "samples": s["samples"],
+                   "ER_rho": var(s["sum_drho"], s["sum_drho2"]) / mu,
+                   "ER_sum_rho_u": float(np.sum(var(s["sum_j"], s["sum_j2"]))) / (3 * kT),
+                   "ER_sum_Pi_aa": float(np.sum(var(s["sum_pi"][:3], s["sum_pi2"][:3]))) / (3 * mu * 2 / 9),
+                   "ER_sum_Pi_ab": float(np.sum(var(s["sum_pi"][3:], s["sum_pi2"][3:]))) / (3 * mu / 9)}
+            sums = sum(lat.sk(f)[0] for f in ("jx", "jy", "jz"))
+            _, counts, ns = lat.sk("jx")
+            k = np.arange(len(sums))
+            sel = (k >= 4) & (k <= 64) & (counts > 0)
+            erk = sums[sel] / counts[sel] / ns / (3 * kT)
+            row["ER_sum_rho_u_k4_64_min"] = float(erk.min())
+            row["ER_sum_rho_u_k4_64_max"] = float(erk.max())
+            row = {k2: (round(v, 5) if isinstance(v, float) else v) for k2, v in row.items()}
+            log(f"table3 {row}")
+            rows.append(row)
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+    return {"box": list(dims), "kT": kT, "burn_in": burn, "steps": steps, "stats_every": every,
+            "sk_every": sk_every, "rows": rows}
+
+
 def profile_run(dims):
     import torch
 
@@ -203,6 +257,9 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--table3", action="store_true",
+                    help="equilibration ratios of Table III at 256^3, kT = 1/3000 (a physics "
+                         "check against the paper, not a throughput figure)")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 2 warm-up and 4 timed steps of the bench "
                          "workload, then one copy of 1 GiB (the counter calibration kernel)")
@@ -215,6 +272,9 @@ def main():
     dims = (args.size,) * 3
     if args.profile:
         profile_run(dims)
+        return
+    if args.table3:
+        print(json.dumps(table3_run()))
         return
     main_run = run_gpu(dims, "f32", 1e-5, args.steps, args.warmup)
     n = dims[0] * dims[1] * dims[2]

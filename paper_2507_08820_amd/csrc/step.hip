@@ -50,15 +50,24 @@ constexpr int kBlock = 256;
 #define RFLBM_ODD_STORE_NT 0
 #endif
 
+// In the odd step the 9 populations with c_x = 0 are shifted only by whole
+// rows, so their accesses do not share cache lines with neighbouring waves.
+#ifndef RFLBM_ODD_ALIGNED_NT
+#define RFLBM_ODD_ALIGNED_NT 0
+#endif
+
+// x_aligned is a constant once the population loop is unrolled.
 template <bool ODD, class P>
-__device__ __forceinline__ auto load_pop(P p) {
-  if constexpr (ODD ? RFLBM_ODD_LOAD_NT : RFLBM_EVEN_LOAD_NT) return __builtin_nontemporal_load(p);
+__device__ __forceinline__ auto load_pop(P p, bool x_aligned) {
+  const bool nt = ODD ? (RFLBM_ODD_LOAD_NT || (x_aligned && RFLBM_ODD_ALIGNED_NT)) : RFLBM_EVEN_LOAD_NT;
+  if (nt) return __builtin_nontemporal_load(p);
   return *p;
 }
 
 template <bool ODD, class T, class P>
-__device__ __forceinline__ void store_pop(T v, P p) {
-  if constexpr (ODD ? RFLBM_ODD_STORE_NT : RFLBM_EVEN_STORE_NT)
+__device__ __forceinline__ void store_pop(T v, P p, bool x_aligned) {
+  const bool nt = ODD ? (RFLBM_ODD_STORE_NT || (x_aligned && RFLBM_ODD_ALIGNED_NT == 1)) : RFLBM_EVEN_STORE_NT;
+  if (nt)
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
