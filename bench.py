@@ -192,6 +192,87 @@ def table3_run(dims=(256, 256, 256), taus=(0.5001, 0.51, 1.0, 10.0, 100.0),
             "sk_every": sk_every, "rows": rows}
 
 
+PROFILE_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -d <out>/prof_trace -o trace --output-format csv "
+             "-- python3 bench.py --profile",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -d <out>/prof_fetch -o fetch --output-format csv "
+             "-- python3 bench.py --profile",
+    "write": "rocprofv3 --pmc WRITE_SIZE -d <out>/prof_write -o write --output-format csv "
+             "-- python3 bench.py --profile",
+}
+
+
+def summarize_profiles(out_dir, dims=(512, 512, 512)):
+    """Writes the profiles/ summaries from the CSVs of the three rocprofv3 runs
+    of `bench.py --profile` (kernel trace, FETCH_SIZE, WRITE_SIZE)."""
+    import csv
+    import glob
+
+    def rows(pattern):
+        files = glob.glob(os.path.join(out_dir, pattern))
+        if not files:
+            raise FileNotFoundError(pattern)
+        with open(files[0]) as fh:
+            return list(csv.DictReader(fh))
+
+    stats = rows("prof_trace/*kernel_stats.csv")
+    fetch = rows("prof_fetch/*counter_collection.csv")
+    write = rows("prof_write/*counter_collection.csv")
+    n = dims[0] * dims[1] * dims[2]
+    algo = BYTES_PER_UPDATE["f32"] * n  # bytes per launch
+    copy_bytes = 1 << 30
+
+    def per_kernel(rs):
+        out = {}
+        for r in rs:
+            name = r["Kernel_Name"]
+            key = ("copy" if "copy_kernel" in name else
+                   "odd" if "step_kernel<0, true" in name else
+                   "even" if "step_kernel<0, false" in name else None)
+            if key:
+                out.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> B
+        return {k: sum(v) / len(v) for k, v in out.items()}
+
+    fb, wb = per_kernel(fetch), per_kernel(write)
+    f_scale, w_scale = copy_bytes / fb["copy"], copy_bytes / wb["copy"]
+    traffic = {k: fb[k] * f_scale + wb[k] * w_scale for k in ("even", "odd")}
+    mean_traffic = (traffic["even"] + traffic["odd"]) / 2
+    dur = {}
+    for r in stats:
+        if "step_kernel<0, true, 10, false>" in r["Name"]:
+            dur["odd"] = float(r["AverageNs"])
+        if "step_kernel<0, false, 10, false>" in r["Name"]:
+            dur["even"] = float(r["AverageNs"])
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("# HBM traffic of the fused step kernel, 512^3 FP32 bench workload\n")
+        fh.write(f"# commands: {PROFILE_CMDS['fetch']}\n#           {PROFILE_CMDS['write']}\n")
+        fh.write("# counters are KiB per dispatch, scaled by what they read for copy_kernel moving 1 GiB\n")
+        fh.write(f"fetch_scale = {f_scale:.5f}\nwrite_scale = {w_scale:.5f}\n")
+        for k in ("even", "odd"):
+            fh.write(f"{k}_fetch_bytes = {fb[k] * f_scale:.0f}\n{k}_write_bytes = {wb[k] * w_scale:.0f}\n")
+            fh.write(f"{k}_traffic_over_algorithmic = {traffic[k] / algo:.4f}\n")
+        fh.write(f"algorithmic_bytes_per_launch = {algo}\n")
+        fh.write(f"hbm_bytes_per_launch = {mean_traffic:.0f}\n")
+        fh.write(f"kernel_source_hash = {kernel_hash()}\n")
+    with open(os.path.join(ROOT, "profiles", "step_f32_512_kernel_trace.txt"), "w") as fh:
+        fh.write("# rocprofv3 kernel statistics, 512^3 FP32 bench workload (bench.py --profile:\n")
+        fh.write("# 2 warm-up + 4 timed steps, one 1 GiB copy)\n")
+        fh.write(f"# command: {PROFILE_CMDS['trace']}\n")
+        fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
+        fh.write("Name | Calls | AverageNs | MinNs | MaxNs\n")
+        for r in stats:
+            if any(t in r["Name"] for t in ("step_kernel", "copy_kernel", "init_eq_kernel")):
+                fh.write(f"{r['Name']} | {r['Calls']} | {float(r['AverageNs']):.0f} | "
+                         f"{r['MinNs']} | {r['MaxNs']}\n")
+        if dur:
+            mean = (dur["even"] + dur["odd"]) / 2
+            fh.write(f"# mean even/odd step kernel: {mean:.0f} ns -> "
+                     f"{algo / (mean * 1e-9) / 1e9:.1f} GB/s algorithmic, "
+                     f"{n / (mean * 1e-9) / 1e6:.0f} MLUPS\n")
+    return traffic, dur
+
+
 def profile_run(dims):
     import torch
 
@@ -260,6 +341,8 @@ def main():
     ap.add_argument("--table3", action="store_true",
                     help="equilibration ratios of Table III at 256^3, kT = 1/3000 (a physics "
                          "check against the paper, not a throughput figure)")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write profiles/ summaries from the rocprofv3 CSVs under DIR")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 2 warm-up and 4 timed steps of the bench "
                          "workload, then one copy of 1 GiB (the counter calibration kernel)")
@@ -270,6 +353,9 @@ def main():
         sys.exit(2)
 
     dims = (args.size,) * 3
+    if args.summarize:
+        print(summarize_profiles(args.summarize))
+        return
     if args.profile:
         profile_run(dims)
         return
