@@ -19,7 +19,8 @@
  * Conventions shared by every call.
  *   Population order: i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1), so the
  *     opposite of i is 26 - i and i = 13 is the rest population.
- *   Node order: n = x + nx (y + ny z); N = nx ny nz must be below 2^32.
+ *   Node order: n = x + nx (y + ny z); N = nx ny nz must be below 2^32 and
+ *     one z plane of populations (27 nx ny values) below 4 GiB.
  *   Population arrays exchanged with the caller are FP64, planar:
  *     f[i * N + n], i = 0..26, and hold the pre-collision state f(x, t) at the
  *     current step count t.
@@ -235,7 +236,8 @@ rflbm_status rflbm_time_steps(rflbm_lattice* lat, int64_t nsteps, double* ms);
  * one buffer and advances all of them by one persistent kernel launch per step
  * (Eq. r-flbe2 at every node of every replica).  Replica r evolves exactly as a
  * stand-alone lattice with params p[r] would, bit for bit.
- * Every replica shares the batch's step count t. */
+ * Every replica shares the batch's step count t; each replica must hold less
+ * than 4 GiB of populations. */
 typedef struct rflbm_batch rflbm_batch;
 
 /* Device bytes for n replicas with params p[0..n-1], 0 if invalid. */

@@ -69,16 +69,16 @@ std::string validate(const rflbm_params* p) {
     return "16-bit storage with kT = 0 needs a storage_scale";
   const uint64_t n = node_count(*p);
   if (n >= (1ull << 32)) return "box has 2^32 or more nodes";
-  if (n * static_cast<uint64_t>(storage_bytes(p->storage)) > (1ull << 32))
-    return "one population plane exceeds 4 GiB (FP32 boxes up to 2^30 nodes, 16-bit up to 2^31)";
+  if (27ull * static_cast<uint64_t>(p->nx) * static_cast<uint64_t>(p->ny) *
+          static_cast<uint64_t>(storage_bytes(p->storage)) >= (1ull << 32))
+    return "one z plane of populations (27 nx ny values) must stay below 4 GiB";
   return "";
 }
 
 Layout layout_for(const rflbm_params& p) {
   Layout L;
   const uint64_t n = node_count(p);
-  L.pitch = align_up(n, 256);
-  L.pop_bytes = align_up(static_cast<size_t>(27) * L.pitch * storage_bytes(p.storage), kAlign);
+  L.pop_bytes = align_up(static_cast<size_t>(27) * n * storage_bytes(p.storage), kAlign);
   L.grid_max = 0;
   for (uint32_t bx : kBlockX) {
     const Launch l = make_launch(p.nx, p.ny, p.nz, bx, 256 / bx);
@@ -112,7 +112,6 @@ void sigma_of(const rflbm_params& p, float sigma[4], float inv[4]) {
 GatherArgs gather_args(const rflbm_lattice* L, const rflbm_params& p, int64_t t) {
   GatherArgs g;
   g.pop = L->buf;
-  g.pitch = L->L.pitch;
   g.nx = p.nx;
   g.ny = p.ny;
   g.nz = p.nz;
@@ -131,7 +130,6 @@ StepArgs step_args(const rflbm_lattice* L) {
   StepArgs a;
   std::memset(&a, 0, sizeof(a));
   a.pop = L->buf;
-  a.pitch = L->L.pitch;
   a.nx = p.nx;
   a.ny = p.ny;
   a.nz = p.nz;

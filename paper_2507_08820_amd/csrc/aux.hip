@@ -5,7 +5,7 @@
 // testing, and a plain copy kernel (bandwidth reference).
 //
 // All of these work on the AA layout described in kernels.hpp: at an even step
-// count f_i(x) sits in plane i at x, at an odd one in plane 26 - i at x - c_i.
+// count f_i(x) sits in slot A[i][x], at an odd one in A[26 - i][x - c_i].
 #include <hip/hip_runtime.h>
 
 #include "d3q27.hpp"
@@ -30,12 +30,19 @@ __device__ __forceinline__ NodeXYZ coords(uint64_t n, uint32_t nx, uint32_t ny) 
   return c;
 }
 
+// Element index of slot A[plane][(x, y, z)] in the x-row blocked layout.
+__device__ __forceinline__ uint64_t element_index(int plane, uint32_t x, uint32_t y, uint32_t z,
+                                                  const GatherArgs& g) {
+  const uint64_t row = y + static_cast<uint64_t>(g.ny) * z;
+  return (row * kQ + plane) * g.nx + x;
+}
+
 // Element index of the slot holding f_i(x) at the given parity.
 __device__ __forceinline__ uint64_t slot_index(int i, NodeXYZ p, const GatherArgs& g) {
-  if (!g.odd) return static_cast<uint64_t>(i) * g.pitch + p.x + g.nx * (p.y + static_cast<uint64_t>(g.ny) * p.z);
+  if (!g.odd) return element_index(i, p.x, p.y, p.z, g);
   const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-  const uint32_t x = wrap_add(p.x, -cx, g.nx), y = wrap_add(p.y, -cy, g.ny), z = wrap_add(p.z, -cz, g.nz);
-  return static_cast<uint64_t>(kQ - 1 - i) * g.pitch + x + g.nx * (y + static_cast<uint64_t>(g.ny) * z);
+  return element_index(kQ - 1 - i, wrap_add(p.x, -cx, g.nx), wrap_add(p.y, -cy, g.ny),
+                       wrap_add(p.z, -cz, g.nz), g);
 }
 
 template <int S>
@@ -206,8 +213,8 @@ __global__ void moments_kernel(const GatherArgs g, uint32_t mask, float* dst) {
   }
 }
 
-// Plane p holds populations of one speed class in either layout (26 - i and i
-// have the same |c|^2), so re-encoding works plane by plane.
+// Slot A[p][.] holds populations of one speed class at either parity (26 - i
+// and i have the same |c|^2), so re-encoding works slot by slot.
 template <int S>
 __global__ void reencode_kernel(const GatherArgs from, const GatherArgs to) {
   using C = Codec<S>;
@@ -217,10 +224,9 @@ __global__ void reencode_kernel(const GatherArgs from, const GatherArgs to) {
   const uint64_t total = N * kQ;
   for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < total;
        e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const int plane = static_cast<int>(e / N);
-    const uint64_t n = e - static_cast<uint64_t>(plane) * N;
+    const int plane = static_cast<int>((e / from.nx) % kQ);
     const int cls = speed_class(plane);
-    T* q = pop + static_cast<uint64_t>(plane) * from.pitch + n;
+    T* q = pop + e;
     const double d = static_cast<double>(C::decode(*q, from.sigma[cls])) +
                      class_weight(cls) * (from.rho0 - to.rho0);
     *q = C::encode(static_cast<float>(d), to.inv_sigma[cls]);

@@ -1,9 +1,11 @@
 // kernels.hpp -- internal interface between the C-ABI layer (api.cpp) and the HIP
 // kernels of the fluctuating lattice Boltzmann step (arXiv:2507.08820, Sec. II).
 //
-// Population storage ("AA" in-place streaming, one lattice copy): 27 planes
-// A[i][n] of `pitch` elements each, n = x + nx (y + ny z), holding the deviation
-// f - w_i rho0 (divided by sigma_class(i) for 16-bit storage).
+// Population storage ("AA" in-place streaming, one lattice copy), blocked by
+// x-rows: the 27 population rows of row r = y + ny z are contiguous, element
+// (i, x) of row r at index (27 r + i) nx + x.  A[i][n] below names that slot of
+// node n = x + nx (y + ny z).  Each slot holds the deviation f - w_i rho0
+// (divided by sigma_class(i) for 16-bit storage).
 //   After an even number t of steps: f_i(x, t) = A[i][x].
 //   After an odd number t of steps:  f_i(x, t) = A[26 - i][x - c_i].
 // An even step reads A[i][x] and writes f*_i(x) to A[26 - i][x]; an odd step
@@ -26,8 +28,7 @@ constexpr int kNumStats = 23;  // per-node statistics accumulated by the step ke
 constexpr int kAccDoubles = 32;  // device accumulator block: 23 sums, samples, mass, momentum
 
 struct StepArgs {
-  void* pop;             // population planes
-  uint64_t pitch;        // elements per plane
+  void* pop;             // populations, x-row blocked
   uint32_t nx, ny, nz;   // box
   uint32_t tiles_x;      // tiles along x (tile = blockDim.x x blockDim.y nodes of one z plane)
   uint32_t tiles_y;      // tiles along y
@@ -94,7 +95,6 @@ hipError_t launch_stats_reduce(const double* partials, uint32_t grid, double* sc
 
 struct GatherArgs {
   const void* pop;
-  uint64_t pitch;
   uint32_t nx, ny, nz;
   uint32_t odd;           // parity of the current step count
   double rho0;

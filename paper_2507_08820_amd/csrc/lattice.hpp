@@ -12,10 +12,9 @@
 
 namespace rflbm {
 
-// Device buffer of one lattice: 27 population planes, then the instability
+// Device buffer of one lattice: the x-row blocked populations, then the instability
 // flag, the FP64 accumulators, the statistics partials and reduction scratch.
 struct Layout {
-  uint64_t pitch;  // elements per plane
   size_t pop_bytes;
   size_t flag_off, acc_off, partial_off, scratch_off, total;
   uint32_t grid_max;

@@ -20,6 +20,8 @@
 // Everything between the 27 loads and the 27 stores stays in registers.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "d3q27.hpp"
 #include "fastdiv.hpp"
 #include "kernels.hpp"
@@ -91,6 +93,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 
   if (active) {
     const uint32_t step = a.step;
+    constexpr bool SMALL_BOX = false;
 #include "node_body.inc"
   } else if constexpr (STATS) {
 #pragma unroll
@@ -126,6 +129,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 template <int S, bool ODD, int ROUNDS>
 __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
   constexpr bool STATS = false;
+  constexpr bool SMALL_BOX = true;  // every replica region is below 4 GiB
   float (*stat_lds)[kBlock] = nullptr;
   const uint32_t tid = 0;
   // the tables are read-only for the whole launch: constant address space,

@@ -58,6 +58,11 @@ def required(dims, **kw):
     return rf.load_library().rflbm_required_bytes(ctypes.byref(p))
 
 
+def test_large_boxes_are_accepted():
+    # 1100 x 1000 x 1000 FP32: 119 GB, one z plane of populations 119 MB
+    assert required((1100, 1000, 1000)) > 27 * 4 * 1100 * 1000 * 1000
+
+
 def test_required_bytes_counts_one_lattice_copy():
     n = 512 ** 3
     b = required((512, 512, 512))
@@ -79,7 +84,7 @@ def test_invalid_parameters_are_rejected(kw):
     assert lib.rflbm_last_error()
 
 
-@pytest.mark.parametrize("dims", [(1, 8, 8), (8, 8, 1), (2048, 2048, 1024), (1100, 1000, 1000)])
+@pytest.mark.parametrize("dims", [(1, 8, 8), (8, 8, 1), (2048, 2048, 1024), (8192, 8192, 2)])
 def test_invalid_boxes_are_rejected(dims):
     assert required(dims) == 0
 

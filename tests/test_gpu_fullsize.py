@@ -6,8 +6,8 @@ lets the oracle collide each source node with its own Philox noise (node
 index, step t), and compares population i of that post-collision state with
 what the GPU stored at y after the step, f_i(y, t + 1) = f*_i(y - c_i, t)
 (Eq. eq:streaming).  Two consecutive steps cover both AA parities.  Boxes:
-the 512^3 benchmark workload (FP32 and FP16 storage), the largest FP32 box the
-library accepts (1024^3, 116 GB), and two replicas of the 64-replica batch.
+the 512^3 benchmark workload (FP32 and FP16 storage), a 1024^3 FP32 box
+(116 GB, 2^30 nodes), and two replicas of the 64-replica batch.
 """
 import numpy as np
 import pytest
@@ -96,9 +96,9 @@ def test_bench_workload_512cube_sampled(rf, ora, storage):
     lat.close()
 
 
-def test_largest_fp32_box_sampled(rf, ora):
+def test_large_fp32_box_sampled(rf, ora):
     dims = (1024, 1024, 1024)
-    print(f"[gpu] largest box {dims}", flush=True)
+    print(f"[gpu] large box {dims}", flush=True)
     lat = rf.Lattice(dims, kT=1e-4, tau=0.7, seed=5)
     lat.init_equilibrium()
     p = ora.make_params(kT=1e-4, tau_shear=0.7, seed=5)
