@@ -94,6 +94,35 @@ def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0):
     return r
 
 
+def precision_study(dims=(128, 128, 128), kts=(1e-4, 1e-5, 1e-6), steps=400, every=2):
+    """<u^2> / (kT / rho0) for FP32, FP16 and BF16 storage with the same seed
+    (the same noise), thermalised start, tau = 0.6: the FP16/BF16 deviation from
+    FP32 isolates the storage precision."""
+    import numpy as np
+    import torch
+
+    import paper_2507_08820_amd as rf
+
+    out = {}
+    for kT in kts:
+        row = {}
+        for storage in ("f32", "f16", "bf16"):
+            lat = rf.Lattice(dims, storage=storage, kT=kT, tau=0.6, seed=21)
+            lat.init_thermal()
+            lat.stats_config(every)
+            lat.step(steps)
+            st = lat.stats()
+            lat.close()
+            n = st["samples"] * st["nodes"]
+            row[storage] = float(np.sum(st["sum_u2"]) / n / (3 * kT))
+        row["f16_minus_f32"] = row["f16"] - row["f32"]
+        row["bf16_minus_f32"] = row["bf16"] - row["f32"]
+        out[f"kT={kT:g}"] = {k: round(v, 6) for k, v in row.items()}
+        log(f"precision kT={kT:g}: {out[f'kT={kT:g}']}")
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batch(storage, steps=200, graph_steps=20):
     """The 64-replica workload: boxes 32^3..96^3, tau in [0.55, 1.2], kT in
     [1e-6, 1e-4], Taylor-Green A = 0.01 per box; aggregate MLUPS of the
@@ -194,7 +223,7 @@ def table3_run(dims=(256, 256, 256), taus=(0.5001, 0.51, 1.0, 10.0, 100.0),
 
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -d <out>/prof_trace -o trace --output-format csv "
-             "-- python3 bench.py --profile",
+             "-- python3 bench.py --steps 60 --warmup 10 --no-extra --no-cpu-baseline",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -d <out>/prof_fetch -o fetch --output-format csv "
              "-- python3 bench.py --profile",
     "write": "rocprofv3 --pmc WRITE_SIZE -d <out>/prof_write -o write --output-format csv "
@@ -256,8 +285,8 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
         fh.write(f"hbm_bytes_per_launch = {mean_traffic:.0f}\n")
         fh.write(f"kernel_source_hash = {kernel_hash()}\n")
     with open(os.path.join(ROOT, "profiles", "step_f32_512_kernel_trace.txt"), "w") as fh:
-        fh.write("# rocprofv3 kernel statistics, 512^3 FP32 bench workload (bench.py --profile:\n")
-        fh.write("# 2 warm-up + 4 timed steps, one 1 GiB copy)\n")
+        fh.write("# rocprofv3 kernel statistics of the benchmark command itself (512^3 FP32\n")
+        fh.write("# workload, 10 warm-up + 60 timed steps; averages include the warm-up steps)\n")
         fh.write(f"# command: {PROFILE_CMDS['trace']}\n")
         fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
         fh.write("Name | Calls | AverageNs | MinNs | MaxNs\n")
@@ -379,6 +408,7 @@ def main():
                            "hbm_gbs": round(BYTES_PER_UPDATE[storage] * n / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
         extra["f16_gain_over_f32"] = round(extra["f16_store"]["mlups"] / main_run["mlups"], 3)
         extra["noise_cost_factor"] = round(extra["reg_lbm_kT0_f32"]["mlups"] / main_run["mlups"], 3)
+        extra["u2_over_kT_by_storage_128cube"] = precision_study()
         extra["batch64_f32"] = run_batch("f32")
         extra["batch64_f16"] = run_batch("f16")
         cc = copy_ceiling()

@@ -87,46 +87,62 @@ def test_shear_wave_decay_with_noise_128cube(rf):
     lat.sync()
 
 
-def thermal_er(rf, ora, storage, kT, dims=(32, 32, 32), steps=400, burn=100, oracle=False):
+def thermal_er(rf, ora, storage, kT, dims=(32, 32, 32), steps=400, sk_every=20, oracle=False):
+    """Thermalised start (the same draw on both sides), tau_s = 0.6, tau_b = 1:
+    equipartition ratios and the momentum S(|n|) / theory per shell."""
     kw = dict(kT=kT, tau=0.6, tau_bulk=1.0, seed=11)
     lat = rf.Lattice(dims, storage=storage, **kw)
-    lat.init_equilibrium()
-    lat.step(burn)
+    lat.init_thermal()
     lat.stats_config(2)
-    lat.step(steps)
+    for _ in range(steps // sk_every):
+        lat.sk_sample()
+        lat.step(sk_every)
     er = er_from_stats(lat.stats(), kT)
+    js = sum(lat.sk(f)[0] for f in ("jx", "jy", "jz"))
+    _, counts, ns = lat.sk("jx")
+    er["sk_j"] = js[1:16] / counts[1:16] / ns / (3 * kT)
     if not oracle:
         return er, None
     p = ora.make_params(kT=kT, tau_shear=0.6, tau_bulk=1.0, seed=11)
-    w = ora.tables()["w"]
-    f = np.tile(w[:, None], (1, int(np.prod(dims))))
-    f = ora.run(p, dims, f, 0, burn)
+    f = ora.init_thermal(p, dims)
     acc = dict(rho=0.0, u2=0.0)
-    n = 0
-    for t in range(burn, burn + steps):
-        if (t - burn) % 2 == 0:
+    spec = 0.0
+    n = nsk = 0
+    for t in range(steps):
+        if t % 2 == 0:
             m = ora.moments(f)
             acc["rho"] += np.var(m["rho"])
             acc["u2"] += np.mean((m["j"] / m["rho"]) ** 2) * 3
             n += 1
+            if t % sk_every == 0:
+                spec = spec + sum(ora.shell_spectrum(m["j"][a], dims, nshells=len(js))[0]
+                                  for a in range(3))
+                nsk += 1
         f = ora.step(p, dims, f, t)
-    ora_er = dict(rho=acc["rho"] / n / (kT / CS2), u2=acc["u2"] / n / (3 * kT))
+    ora_er = dict(rho=acc["rho"] / n / (kT / CS2), u2=acc["u2"] / n / (3 * kT),
+                  sk_j=spec[1:16] / counts[1:16] / nsk / (3 * kT))
     return er, ora_er
 
 
 @pytest.mark.parametrize("kT", [1e-4, 1e-5, 1e-6])
 def test_storage_precision_equipartition(rf, ora, kT):
     """Same seed, same noise: the FP32, FP16 and BF16 runs and the FP64 oracle
-    follow the same trajectory up to rounding, so differences in <u^2> measure
-    the storage precision alone; each must also be within 1 % of theory."""
+    follow the same trajectory up to rounding, so differences in <u^2> and in
+    S(|n|) measure the storage precision alone; each must also be within 1 %
+    (u^2) of theory."""
     er32, er64 = thermal_er(rf, ora, "f32", kT, oracle=True)
     er16, _ = thermal_er(rf, ora, "f16", kT)
     erbf, _ = thermal_er(rf, ora, "bf16", kT)
+    dsk = {name: float(np.max(np.abs(e["sk_j"] - er64["sk_j"]))) for name, e in
+           (("f32", er32), ("f16", er16), ("bf16", erbf))}
     print(f"[gpu] kT={kT}: ER(u2) oracle {er64['u2']:.5f} f32 {er32['u2']:.5f} "
           f"f16 {er16['u2']:.5f} bf16 {erbf['u2']:.5f}; ER(rho) oracle {er64['rho']:.5f} "
-          f"f32 {er32['rho']:.5f} f16 {er16['rho']:.5f} bf16 {erbf['rho']:.5f}", flush=True)
+          f"f32 {er32['rho']:.5f} f16 {er16['rho']:.5f} bf16 {erbf['rho']:.5f}; "
+          f"max |S_j(n) - S_j,oracle(n)| / theory over shells 1..15: {dsk}", flush=True)
     assert abs(er32["u2"] - er64["u2"]) < 1e-4
     assert abs(er16["u2"] - er64["u2"]) < 2e-3
+    assert dsk["f32"] < 1e-3
+    assert dsk["f16"] < 2e-2
     for er in (er32, er16, erbf):
         assert abs(er["u2"] - 1) < 0.01
         assert abs(er["rho"] - 1) < 0.02
