@@ -251,13 +251,21 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
     algo = BYTES_PER_UPDATE["f32"] * n  # bytes per launch
     copy_bytes = 1 << 30
 
+    def kind(name):
+        # FP32, Philox-10, no statistics: the even step is the tiled kernel, the
+        # odd step the whole-row kernel (or the tiled one when rows are off)
+        if "copy_kernel" in name:
+            return "copy"
+        if "step_row_kernel<0, 10>" in name or "step_kernel<0, true, 10, false>" in name:
+            return "odd"
+        if "step_kernel<0, false, 10, false>" in name:
+            return "even"
+        return None
+
     def per_kernel(rs):
         out = {}
         for r in rs:
-            name = r["Kernel_Name"]
-            key = ("copy" if "copy_kernel" in name else
-                   "odd" if "step_kernel<0, true" in name else
-                   "even" if "step_kernel<0, false" in name else None)
+            key = kind(r["Kernel_Name"])
             if key:
                 out.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> B
         return {k: sum(v) / len(v) for k, v in out.items()}
@@ -268,10 +276,9 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
     mean_traffic = (traffic["even"] + traffic["odd"]) / 2
     dur = {}
     for r in stats:
-        if "step_kernel<0, true, 10, false>" in r["Name"]:
-            dur["odd"] = float(r["AverageNs"])
-        if "step_kernel<0, false, 10, false>" in r["Name"]:
-            dur["even"] = float(r["AverageNs"])
+        key = kind(r["Name"])
+        if key in ("even", "odd"):
+            dur[key] = float(r["AverageNs"])
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:
         fh.write("# HBM traffic of the fused step kernel, 512^3 FP32 bench workload\n")
@@ -291,7 +298,7 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
         fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
         fh.write("Name | Calls | AverageNs | MinNs | MaxNs\n")
         for r in stats:
-            if any(t in r["Name"] for t in ("step_kernel", "copy_kernel", "init_eq_kernel")):
+            if any(t in r["Name"] for t in ("step_kernel", "step_row_kernel", "copy_kernel", "init_eq_kernel")):
                 fh.write(f"{r['Name']} | {r['Calls']} | {float(r['AverageNs']):.0f} | "
                          f"{r['MinNs']} | {r['MaxNs']}\n")
         if dur:

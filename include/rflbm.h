@@ -225,6 +225,18 @@ rflbm_status rflbm_reset_sk(rflbm_lattice* lat);
 rflbm_status rflbm_set_launch(rflbm_lattice* lat, int32_t bx, int32_t xcd_remap);
 rflbm_status rflbm_get_launch(const rflbm_lattice* lat, int32_t* bx, int32_t* xcd_remap);
 
+/* Whole-row odd steps (the streaming of Eq. eq:streaming in its odd AA
+ * phase).  When enabled and nx is a multiple of 64 no larger than 1024, every
+ * odd step without statistics runs one block per x-row, so that the shifts by
+ * c_x = +-1 stay inside a block (values move between lanes) and every load and
+ * store covers whole aligned cache lines; other steps keep the tiled shape of
+ * rflbm_set_launch.  Results are bit for bit the same either way.  Enabled by
+ * rflbm_create for FP32 storage, disabled for FP16/BF16 (whose step is bound
+ * by arithmetic rather than bandwidth).  rflbm_get_row_blocks sets *active to
+ * 1 when odd steps take that form. */
+rflbm_status rflbm_set_row_blocks(rflbm_lattice* lat, int32_t enable);
+rflbm_status rflbm_get_row_blocks(const rflbm_lattice* lat, int32_t* active);
+
 /* Times nsteps steps with HIP events recorded on the lattice's own stream and
  * waits for them; *ms gets the elapsed milliseconds.  Used by benchmarks. */
 rflbm_status rflbm_time_steps(rflbm_lattice* lat, int64_t nsteps, double* ms);

@@ -94,6 +94,8 @@ _SIGS = {
     "rflbm_reset_sk": (ctypes.c_int, [_VP]),
     "rflbm_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "rflbm_get_launch": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "rflbm_set_row_blocks": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "rflbm_get_row_blocks": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "rflbm_time_steps": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "rflbm_batch_required_bytes": (ctypes.c_size_t, [ctypes.c_int32, _PP]),
     "rflbm_batch_create": (ctypes.c_int, [ctypes.c_int32, _PP, _VP, ctypes.c_size_t, _VP,
@@ -322,6 +324,16 @@ class Lattice:
         bx, remap = ctypes.c_int32(), ctypes.c_int32()
         check(self.lib.rflbm_get_launch(self._h, ctypes.byref(bx), ctypes.byref(remap)))
         return bx.value, bool(remap.value)
+
+    def set_row_blocks(self, enable=True):
+        check(self.lib.rflbm_set_row_blocks(self._h, int(bool(enable))))
+
+    @property
+    def row_blocks(self) -> bool:
+        """True when odd steps run in whole-row blocks (aligned full-line stores)."""
+        active = ctypes.c_int32()
+        check(self.lib.rflbm_get_row_blocks(self._h, ctypes.byref(active)))
+        return bool(active.value)
 
     def time_steps(self, nsteps) -> float:
         ms = ctypes.c_double()

@@ -69,16 +69,27 @@ std::string validate(const rflbm_params* p) {
     return "16-bit storage with kT = 0 needs a storage_scale";
   const uint64_t n = node_count(*p);
   if (n >= (1ull << 32)) return "box has 2^32 or more nodes";
-  if (27ull * static_cast<uint64_t>(p->nx) * static_cast<uint64_t>(p->ny) *
-          static_cast<uint64_t>(storage_bytes(p->storage)) >= (1ull << 32))
+  if (static_cast<uint64_t>(p->ny) * row_pitch_of(*p) >= (1ull << 32))
     return "one z plane of populations (27 nx ny values) must stay below 4 GiB";
   return "";
 }
 
+uint64_t pop_pitch_of(const rflbm_params& p) {
+  return static_cast<uint64_t>(p.nx) * storage_bytes(p.storage) + RFLBM_POP_PAD;
+}
+
+uint64_t row_pitch_of(const rflbm_params& p) { return 27ull * pop_pitch_of(p) + RFLBM_ROW_PAD; }
+
+uint64_t plane_pitch_of(const rflbm_params& p) {
+  return static_cast<uint64_t>(p.ny) * row_pitch_of(p) + RFLBM_PLANE_PAD;
+}
+
 Layout layout_for(const rflbm_params& p) {
   Layout L;
-  const uint64_t n = node_count(p);
-  L.pop_bytes = align_up(static_cast<size_t>(27) * n * storage_bytes(p.storage), kAlign);
+  L.pop_pitch = static_cast<uint32_t>(pop_pitch_of(p));
+  L.row_pitch = static_cast<uint32_t>(row_pitch_of(p));
+  L.plane_pitch = plane_pitch_of(p);
+  L.pop_bytes = align_up(static_cast<size_t>(p.nz) * L.plane_pitch, kAlign);
   L.grid_max = 0;
   for (uint32_t bx : kBlockX) {
     const Launch l = make_launch(p.nx, p.ny, p.nz, bx, 256 / bx);
@@ -115,6 +126,9 @@ GatherArgs gather_args(const rflbm_lattice* L, const rflbm_params& p, int64_t t)
   g.nx = p.nx;
   g.ny = p.ny;
   g.nz = p.nz;
+  g.pop_pitch = L->L.pop_pitch / storage_bytes(p.storage);
+  g.row_pitch = L->L.row_pitch / storage_bytes(p.storage);
+  g.plane_pitch = L->L.plane_pitch / storage_bytes(p.storage);
   g.odd = static_cast<uint32_t>(t & 1);
   g.rho0 = p.rho0;
   sigma_of(p, g.sigma, g.inv_sigma);
@@ -133,6 +147,9 @@ StepArgs step_args(const rflbm_lattice* L) {
   a.nx = p.nx;
   a.ny = p.ny;
   a.nz = p.nz;
+  a.pop_pitch = L->L.pop_pitch;
+  a.row_pitch = L->L.row_pitch;
+  a.plane_pitch = L->L.plane_pitch;
   a.tiles_x = (p.nx + L->launch.bx - 1) / L->launch.bx;
   a.tiles_y = (p.ny + L->launch.by - 1) / L->launch.by;
   a.ntiles = a.tiles_x * a.tiles_y * static_cast<uint32_t>(p.nz);
@@ -170,6 +187,9 @@ void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStre
   L->stream = s;
   L->launch = make_launch(p.nx, p.ny, p.nz, p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64),
                           p.nx >= 256 ? 1 : (p.nx >= 128 ? 2 : 4));
+  // whole-row odd steps pay off where the step is bandwidth bound (FP32); the
+  // 16-bit steps are bound by arithmetic, where the lane moves cost more
+  L->row_odd = p.storage == RFLBM_F32;
 }
 
 hipError_t lattice_clear(rflbm_lattice* L) {
@@ -255,7 +275,11 @@ rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps) {
     const int64_t t = L->t;
     const bool stats = L->stats_every > 0 && (t % L->stats_every) == 0;
     a.step = static_cast<uint32_t>(t & 0xffffffffu);
-    RFLBM_HIP(launch_step(L->p.storage, (t & 1) != 0, rounds, stats, a, L->launch, L->stream));
+    const bool odd = (t & 1) != 0;
+    if (odd && !stats && L->row_odd && row_kernel_fits(L->p.nx))
+      RFLBM_HIP(launch_step_row(L->p.storage, rounds, a, L->stream));
+    else
+      RFLBM_HIP(launch_step(L->p.storage, odd, rounds, stats, a, L->launch, L->stream));
     if (stats) RFLBM_HIP(launch_stats_reduce(a.partials, L->launch.grid, scratch, acc, L->stream));
     L->t = t + 1;
   }
@@ -602,6 +626,19 @@ rflbm_status rflbm_get_launch(const rflbm_lattice* L, int32_t* bx, int32_t* xcd_
   if (rflbm_status s = check_lattice(L)) return s;
   if (bx) *bx = static_cast<int32_t>(L->launch.bx);
   if (xcd_remap) *xcd_remap = L->xcd_remap ? 1 : 0;
+  return RFLBM_OK;
+}
+
+rflbm_status rflbm_set_row_blocks(rflbm_lattice* L, int32_t enable) {
+  if (rflbm_status s = check_lattice(L)) return s;
+  L->row_odd = enable != 0;
+  return RFLBM_OK;
+}
+
+rflbm_status rflbm_get_row_blocks(const rflbm_lattice* L, int32_t* active) {
+  if (rflbm_status s = check_lattice(L)) return s;
+  if (!active) return fail(RFLBM_EINVAL, "active is NULL");
+  *active = L->row_odd && row_kernel_fits(L->p.nx) ? 1 : 0;
   return RFLBM_OK;
 }
 

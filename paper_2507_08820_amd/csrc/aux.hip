@@ -33,8 +33,7 @@ __device__ __forceinline__ NodeXYZ coords(uint64_t n, uint32_t nx, uint32_t ny) 
 // Element index of slot A[plane][(x, y, z)] in the x-row blocked layout.
 __device__ __forceinline__ uint64_t element_index(int plane, uint32_t x, uint32_t y, uint32_t z,
                                                   const GatherArgs& g) {
-  const uint64_t row = y + static_cast<uint64_t>(g.ny) * z;
-  return (row * kQ + plane) * g.nx + x;
+  return z * g.plane_pitch + y * g.row_pitch + static_cast<uint64_t>(plane) * g.pop_pitch + x;
 }
 
 // Element index of the slot holding f_i(x) at the given parity.
@@ -224,9 +223,14 @@ __global__ void reencode_kernel(const GatherArgs from, const GatherArgs to) {
   const uint64_t total = N * kQ;
   for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < total;
        e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const int plane = static_cast<int>((e / from.nx) % kQ);
+    // e runs over (x, plane, y, z) with x fastest; padding is left untouched
+    const uint32_t x = static_cast<uint32_t>(e % from.nx);
+    const uint64_t r = e / from.nx;
+    const int plane = static_cast<int>(r % kQ);
+    const uint64_t row = r / kQ;
     const int cls = speed_class(plane);
-    T* q = pop + e;
+    T* q = pop + element_index(plane, x, static_cast<uint32_t>(row % from.ny),
+                               static_cast<uint32_t>(row / from.ny), from);
     const double d = static_cast<double>(C::decode(*q, from.sigma[cls])) +
                      class_weight(cls) * (from.rho0 - to.rho0);
     *q = C::encode(static_cast<float>(d), to.inv_sigma[cls]);

@@ -66,7 +66,7 @@ std::string validate_batch(int32_t n, const rflbm_params* p) {
     if (!e.empty()) return "replica " + std::to_string(r) + ": " + e;
     if (p[r].storage != p[0].storage) return "every replica must use the same storage type";
     if (p[r].philox_rounds != p[0].philox_rounds) return "every replica must use the same Philox rounds";
-    if (27ull * node_count(p[r]) * static_cast<uint64_t>(storage_bytes(p[r].storage)) >= (1ull << 32))
+    if (static_cast<uint64_t>(p[r].nz) * plane_pitch_of(p[r]) >= (1ull << 32))
       return "replica " + std::to_string(r) + ": a batch replica must hold less than 4 GiB of populations";
     tiles += (node_count(p[r]) + 127) / 128;
   }

@@ -3,8 +3,10 @@
 //
 // Population storage ("AA" in-place streaming, one lattice copy), blocked by
 // x-rows: the 27 population rows of row r = y + ny z are contiguous, element
-// (i, x) of row r at index (27 r + i) nx + x.  A[i][n] below names that slot of
-// node n = x + nx (y + ny z).  Each slot holds the deviation f - w_i rho0
+// (i, x) of row (y, z) at index z P + y R + i Q + x, with population-row pitch
+// Q >= nx, row pitch R >= 27 Q and plane pitch P >= ny R (padding, if any, at
+// the end of each population row, row block and plane).  A[i][n] below names
+// that slot of node n = x + nx (y + ny z).  Each slot holds the deviation f - w_i rho0
 // (divided by sigma_class(i) for 16-bit storage).
 //   After an even number t of steps: f_i(x, t) = A[i][x].
 //   After an odd number t of steps:  f_i(x, t) = A[26 - i][x - c_i].
@@ -23,6 +25,7 @@ namespace rflbm {
 
 enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
+constexpr uint32_t kMaxRowWaves = 16;  // whole-row odd step: nx <= 1024
 constexpr int kNumStats = 23;  // per-node statistics accumulated by the step kernel
 // column layout: 0 drho, 1 drho^2, 2-4 j, 5-7 j^2, 8-10 u^2, 11-16 Pi, 17-22 Pi^2
 constexpr int kAccDoubles = 32;  // device accumulator block: 23 sums, samples, mass, momentum
@@ -30,6 +33,9 @@ constexpr int kAccDoubles = 32;  // device accumulator block: 23 sums, samples, 
 struct StepArgs {
   void* pop;             // populations, x-row blocked
   uint32_t nx, ny, nz;   // box
+  uint32_t pop_pitch;    // bytes from population row i to row i + 1 of one x-row block
+  uint32_t row_pitch;    // bytes from one x-row block (27 population rows) to the next in y
+  uint64_t plane_pitch;  // bytes from one z plane of row blocks to the next
   uint32_t tiles_x;      // tiles along x (tile = blockDim.x x blockDim.y nodes of one z plane)
   uint32_t tiles_y;      // tiles along y
   uint32_t ntiles;       // tiles_x * tiles_y * nz
@@ -88,6 +94,13 @@ Launch make_launch(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t bx, uint32_t 
 hipError_t launch_step(int storage, bool odd, int rounds, bool stats, const StepArgs& a,
                        const Launch& l, hipStream_t stream);
 
+// True when the odd step can run in whole-row blocks: nx a multiple of 64, at
+// most 64 kMaxRowWaves.
+bool row_kernel_fits(uint32_t nx);
+// Odd step without statistics, one block per x-row (a.xcd_remap applies to
+// rows); every store is a whole aligned cache line.
+hipError_t launch_step_row(int storage, int rounds, const StepArgs& a, hipStream_t stream);
+
 // Deterministic reduction of the statistics partials into the accumulators.
 // scratch holds at least 2 * kNumStats * ceil(grid / 2048) doubles.
 hipError_t launch_stats_reduce(const double* partials, uint32_t grid, double* scratch,
@@ -96,6 +109,9 @@ hipError_t launch_stats_reduce(const double* partials, uint32_t grid, double* sc
 struct GatherArgs {
   const void* pop;
   uint32_t nx, ny, nz;
+  uint64_t pop_pitch;     // elements from population row i to row i + 1 of a block
+  uint64_t row_pitch;     // elements from one x-row block to the next in y
+  uint64_t plane_pitch;   // elements from one z plane to the next
   uint32_t odd;           // parity of the current step count
   double rho0;
   float sigma[4];

@@ -15,6 +15,9 @@ namespace rflbm {
 // Device buffer of one lattice: the x-row blocked populations, then the instability
 // flag, the FP64 accumulators, the statistics partials and reduction scratch.
 struct Layout {
+  uint32_t pop_pitch;    // bytes between the population rows of one x-row block
+  uint32_t row_pitch;    // bytes between x-row blocks (27 population rows) in y
+  uint64_t plane_pitch;  // bytes between z planes
   size_t pop_bytes;
   size_t flag_off, acc_off, partial_off, scratch_off, total;
   uint32_t grid_max;
@@ -22,10 +25,27 @@ struct Layout {
 
 constexpr size_t kAlign = 256;
 
+// Padding (bytes) appended to every population row, every x-row block and
+// every z plane of the population array.
+#ifndef RFLBM_POP_PAD
+#define RFLBM_POP_PAD 0
+#endif
+#ifndef RFLBM_ROW_PAD
+#define RFLBM_ROW_PAD 0
+#endif
+#ifndef RFLBM_PLANE_PAD
+#define RFLBM_PLANE_PAD 0
+#endif
+static_assert(RFLBM_POP_PAD % 128 == 0 && RFLBM_ROW_PAD % 256 == 0 && RFLBM_PLANE_PAD % 256 == 0,
+              "pads keep rows aligned to cache lines");
+
 size_t align_up(size_t v, size_t a);
 uint64_t node_count(const rflbm_params& p);
 std::string validate(const rflbm_params* p);
 Layout layout_for(const rflbm_params& p);
+uint64_t pop_pitch_of(const rflbm_params& p);    // bytes between population rows
+uint64_t row_pitch_of(const rflbm_params& p);    // bytes between x-row blocks
+uint64_t plane_pitch_of(const rflbm_params& p);  // bytes between z planes
 rflbm_status fail(rflbm_status st, const std::string& msg);
 
 }  // namespace rflbm
@@ -41,6 +61,7 @@ struct rflbm_lattice {
   int32_t stats_every = 0;
   rflbm::Launch launch{};
   bool xcd_remap = true;
+  bool row_odd = true;  // odd steps without statistics in whole-row blocks when nx fits (FP32 default)
   // S(k) state (library-allocated on first use)
   hipfftHandle plan = 0;
   bool have_plan = false;

@@ -66,6 +66,67 @@ __device__ __forceinline__ auto load_pop(P p, bool x_aligned) {
   return *p;
 }
 
+// Loads and stores of the whole-row odd step: whole aligned cache lines that
+// no other wave touches, like those of the even step.
+#ifndef RFLBM_ROW_LOAD_NT
+#define RFLBM_ROW_LOAD_NT 1
+#endif
+#ifndef RFLBM_ROW_STORE_NT
+#define RFLBM_ROW_STORE_NT 1
+#endif
+
+template <class P>
+__device__ __forceinline__ auto load_row_pop(P p) {
+  if (RFLBM_ROW_LOAD_NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
+template <class T, class P>
+__device__ __forceinline__ void store_row_pop(T v, P p) {
+  if (RFLBM_ROW_STORE_NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Whole-row blocks (blockDim.x = nx, so lane = x mod 64): replaces v[i], for
+// every population with c_x = +-1, by the word that lane x - c_x holds.
+// Inside a wave that is a rotation by one lane; the one word per wave and
+// population that crosses into the neighbouring wave (periodically, from the
+// last wave into the first) goes through `edge` (18 x kMaxRowWaves words of
+// LDS, used once per call site).  Ends with a block barrier.  Moving raw bit
+// patterns keeps the arithmetic around the move identical to the tiled step's.
+__device__ __forceinline__ void row_shift(uint32_t (&v)[kQ], uint32_t (*edge)[kMaxRowWaves], uint32_t x,
+                                          uint32_t nx) {
+  const uint32_t lane = x & 63u, wave = x >> 6, nwave = nx >> 6;
+  // edge slot of population i with c_x = -1 (i = 3 k): 2 k; c_x = +1 (i = 3 k + 2): 2 k + 1
+  if (lane == 63u) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) edge[2 * k + 1][wave] = v[3 * k + 2];
+  }
+  if (lane == 0u) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) edge[2 * k][wave] = v[3 * k];
+  }
+  const int from_left = static_cast<int>((lane + 63u) & 63u), from_right = static_cast<int>((lane + 1u) & 63u);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    v[3 * k + 2] = __shfl(v[3 * k + 2], from_left);
+    v[3 * k] = __shfl(v[3 * k], from_right);
+  }
+  __syncthreads();
+  if (lane == 0u) {
+    const uint32_t wprev = wave == 0 ? nwave - 1 : wave - 1;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[3 * k + 2] = edge[2 * k + 1][wprev];
+  }
+  if (lane == 63u) {
+    const uint32_t wnext = wave + 1 == nwave ? 0 : wave + 1;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[3 * k] = edge[2 * k][wnext];
+  }
+}
+
 template <bool ODD, class T, class P>
 __device__ __forceinline__ void store_pop(T v, P p, bool x_aligned) {
   const bool nt = ODD ? (RFLBM_ODD_STORE_NT || (x_aligned && RFLBM_ODD_ALIGNED_NT == 1)) : RFLBM_EVEN_STORE_NT;
@@ -94,6 +155,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
   if (active) {
     const uint32_t step = a.step;
     constexpr bool SMALL_BOX = false;
+    constexpr bool ROW_SHIFT = false;
+    [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
+    [[maybe_unused]] uint32_t (*row_edge_out)[kMaxRowWaves] = nullptr;
 #include "node_body.inc"
   } else if constexpr (STATS) {
 #pragma unroll
@@ -121,6 +185,27 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
   }
 }
 
+// Odd step of one box in whole-row blocks: block b covers the x-row (y, z) of
+// row index y + ny z (blockDim.x = nx, a multiple of 64 up to 1024), so that
+// the +-1 shifts in x stay inside the block and every load and store is a
+// whole aligned cache line (see row_shift).  Without statistics.
+template <int S, int ROUNDS>
+__global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepArgs a) {
+  constexpr bool ODD = true, STATS = false, SMALL_BOX = false, ROW_SHIFT = true;
+  [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
+  [[maybe_unused]] const uint32_t tid = 0;
+  __shared__ uint32_t row_edge_in[18][kMaxRowWaves];   // gather (stored words)
+  __shared__ uint32_t row_edge_out[18][kMaxRowWaves];  // scatter (FP32 values)
+  uint32_t row = blockIdx.x;
+  if (a.xcd_remap) row = (row & 7u) * (gridDim.x >> 3) + (row >> 3);
+  if (row >= a.ny * a.nz) return;  // the whole block: rounding of the grid to 8
+  const uint32_t x = threadIdx.x;
+  const uint32_t y = row % a.ny;
+  const uint32_t z = row / a.ny;
+  const uint32_t step = a.step;
+#include "node_body.inc"
+}
+
 // Many boxes: tile t holds blockDim.x consecutive nodes (flattened index) of
 // replica tile_rep[t]; a persistent grid walks the tiles.  The step count (the
 // Philox counter) comes from device memory so that a captured graph of several
@@ -130,6 +215,9 @@ template <int S, bool ODD, int ROUNDS>
 __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
   constexpr bool STATS = false;
   constexpr bool SMALL_BOX = true;  // every replica region is below 4 GiB
+  constexpr bool ROW_SHIFT = false;
+  [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
+  [[maybe_unused]] uint32_t (*row_edge_out)[kMaxRowWaves] = nullptr;
   float (*stat_lds)[kBlock] = nullptr;
   const uint32_t tid = 0;
   // the tables are read-only for the whole launch: constant address space,
@@ -218,7 +306,34 @@ hipError_t launch_s(bool odd, int rounds, bool stats, const StepArgs& a, const L
   return stats ? launch_r<S, false, true>(rounds, a, l, s) : launch_r<S, false, false>(rounds, a, l, s);
 }
 
+template <int S>
+hipError_t launch_row_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_t s) {
+  const dim3 g(grid), blk(a.nx);
+  switch (rounds) {
+    case 0: hipLaunchKernelGGL((step_row_kernel<S, 0>), g, blk, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((step_row_kernel<S, 7>), g, blk, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((step_row_kernel<S, 10>), g, blk, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+bool row_kernel_fits(uint32_t nx) { return nx % 64 == 0 && nx >= 64 && nx <= kMaxRowWaves * 64; }
+
+hipError_t launch_step_row(int storage, int rounds, const StepArgs& a, hipStream_t stream) {
+  if (!row_kernel_fits(a.nx)) return hipErrorInvalidConfiguration;
+  const uint64_t rows = static_cast<uint64_t>(a.ny) * a.nz;
+  if (rows >= (1ull << 31)) return hipErrorInvalidConfiguration;
+  const uint32_t grid = static_cast<uint32_t>((rows + 7) / 8 * 8);
+  switch (storage) {
+    case kF32: return launch_row_s<kF32>(rounds, a, grid, stream);
+    case kF16: return launch_row_s<kF16>(rounds, a, grid, stream);
+    case kBF16: return launch_row_s<kBF16>(rounds, a, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 Launch make_launch(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t bx, uint32_t by) {
   Launch l;

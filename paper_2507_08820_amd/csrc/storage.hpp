@@ -50,6 +50,18 @@ struct Codec<kBF16> {
 // Byte size of one stored value.
 constexpr int storage_bytes(int s) { return s == kF32 ? 4 : 2; }
 
+// A stored element as a 32-bit word (16-bit types zero-extended) and back.
+template <class T>
+__device__ __forceinline__ uint32_t to_bits(T q) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(uint32_t, q);
+  else return __builtin_bit_cast(uint16_t, q);
+}
+template <class T>
+__device__ __forceinline__ T from_bits(uint32_t b) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, b);
+  else return __builtin_bit_cast(T, static_cast<uint16_t>(b));
+}
+
 // Periodic neighbour coordinate: c in {-1, 0, 1}.
 __host__ __device__ __forceinline__ uint32_t wrap_add(uint32_t x, int c, uint32_t n) {
   return c == 0 ? x : (c > 0 ? (x + 1 == n ? 0u : x + 1) : (x == 0 ? n - 1 : x - 1));

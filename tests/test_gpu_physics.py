@@ -6,7 +6,9 @@
 - shear-wave decay at nu = cs2 (tau - 1/2) with thermal noise on (128^3,
   tau_s = 0.8, tau_b = 1, kT = 1e-5);
 - storage precision: FP16 and BF16 deviation storage against FP32 and against
-  the FP64 oracle run with the same noise, kT in {1e-4, 1e-5, 1e-6}.
+  the FP64 oracle run with the same noise, kT in {1e-4, 1e-5, 1e-6}: <u^2>,
+  <d rho^2> and the momentum S(|n|) at 32^3 (shells 1..15) and at 128^3
+  (shells 4..64).
 """
 import numpy as np
 import pytest
@@ -87,9 +89,10 @@ def test_shear_wave_decay_with_noise_128cube(rf):
     lat.sync()
 
 
-def thermal_er(rf, ora, storage, kT, dims=(32, 32, 32), steps=400, sk_every=20, oracle=False):
+def thermal_er(rf, ora, storage, kT, dims, steps, shells, sk_every=20, oracle=False):
     """Thermalised start (the same draw on both sides), tau_s = 0.6, tau_b = 1:
-    equipartition ratios and the momentum S(|n|) / theory per shell."""
+    equipartition ratios and the momentum S(|n|) / theory on the given shells."""
+    lo, hi = shells
     kw = dict(kT=kT, tau=0.6, tau_bulk=1.0, seed=11)
     lat = rf.Lattice(dims, storage=storage, **kw)
     lat.init_thermal()
@@ -100,7 +103,9 @@ def thermal_er(rf, ora, storage, kT, dims=(32, 32, 32), steps=400, sk_every=20, 
     er = er_from_stats(lat.stats(), kT)
     js = sum(lat.sk(f)[0] for f in ("jx", "jy", "jz"))
     _, counts, ns = lat.sk("jx")
-    er["sk_j"] = js[1:16] / counts[1:16] / ns / (3 * kT)
+    lat.sync()
+    lat.close()
+    er["sk_j"] = js[lo:hi + 1] / counts[lo:hi + 1] / ns / (3 * kT)
     if not oracle:
         return er, None
     p = ora.make_params(kT=kT, tau_shear=0.6, tau_bulk=1.0, seed=11)
@@ -120,25 +125,33 @@ def thermal_er(rf, ora, storage, kT, dims=(32, 32, 32), steps=400, sk_every=20, 
                 nsk += 1
         f = ora.step(p, dims, f, t)
     ora_er = dict(rho=acc["rho"] / n / (kT / CS2), u2=acc["u2"] / n / (3 * kT),
-                  sk_j=spec[1:16] / counts[1:16] / nsk / (3 * kT))
+                  sk_j=spec[lo:hi + 1] / counts[lo:hi + 1] / nsk / (3 * kT))
     return er, ora_er
+
+
+def precision_case(rf, ora, kT, dims, steps, shells):
+    """Same seed, same noise: the FP32, FP16 and BF16 runs and the FP64 oracle
+    follow the same trajectory up to rounding, so differences in <u^2> and in
+    S(|n|) measure the storage precision alone."""
+    er32, er64 = thermal_er(rf, ora, "f32", kT, dims, steps, shells, oracle=True)
+    er16, _ = thermal_er(rf, ora, "f16", kT, dims, steps, shells)
+    erbf, _ = thermal_er(rf, ora, "bf16", kT, dims, steps, shells)
+    ers = (("oracle", er64), ("f32", er32), ("f16", er16), ("bf16", erbf))
+    dsk = {name: float(np.max(np.abs(e["sk_j"] - er64["sk_j"]))) for name, e in ers[1:]}
+    print(f"[gpu] {dims[0]}^3 kT={kT}: ER(u2) " +
+          " ".join(f"{k} {e['u2']:.6f}" for k, e in ers) + "; ER(rho) " +
+          " ".join(f"{k} {e['rho']:.6f}" for k, e in ers) +
+          f"; mean S_j/theory on shells {shells[0]}..{shells[1]}: " +
+          " ".join(f"{k} {np.mean(e['sk_j']):.5f}" for k, e in ers) +
+          f"; max |S_j - S_j,oracle| / theory: {dsk}", flush=True)
+    return er64, er32, er16, erbf, dsk
 
 
 @pytest.mark.parametrize("kT", [1e-4, 1e-5, 1e-6])
 def test_storage_precision_equipartition(rf, ora, kT):
-    """Same seed, same noise: the FP32, FP16 and BF16 runs and the FP64 oracle
-    follow the same trajectory up to rounding, so differences in <u^2> and in
-    S(|n|) measure the storage precision alone; each must also be within 1 %
-    (u^2) of theory."""
-    er32, er64 = thermal_er(rf, ora, "f32", kT, oracle=True)
-    er16, _ = thermal_er(rf, ora, "f16", kT)
-    erbf, _ = thermal_er(rf, ora, "bf16", kT)
-    dsk = {name: float(np.max(np.abs(e["sk_j"] - er64["sk_j"]))) for name, e in
-           (("f32", er32), ("f16", er16), ("bf16", erbf))}
-    print(f"[gpu] kT={kT}: ER(u2) oracle {er64['u2']:.5f} f32 {er32['u2']:.5f} "
-          f"f16 {er16['u2']:.5f} bf16 {erbf['u2']:.5f}; ER(rho) oracle {er64['rho']:.5f} "
-          f"f32 {er32['rho']:.5f} f16 {er16['rho']:.5f} bf16 {erbf['rho']:.5f}; "
-          f"max |S_j(n) - S_j,oracle(n)| / theory over shells 1..15: {dsk}", flush=True)
+    """32^3, 400 steps, shells 1..15: FP32 and FP16 against the FP64 oracle on
+    the same noise; every precision within 1 % of theory for <u^2>."""
+    er64, er32, er16, erbf, dsk = precision_case(rf, ora, kT, (32, 32, 32), 400, (1, 15))
     assert abs(er32["u2"] - er64["u2"]) < 1e-4
     assert abs(er16["u2"] - er64["u2"]) < 2e-3
     assert dsk["f32"] < 1e-3
@@ -147,3 +160,19 @@ def test_storage_precision_equipartition(rf, ora, kT):
         assert abs(er["u2"] - 1) < 0.01
         assert abs(er["rho"] - 1) < 0.02
     assert abs(erbf["u2"] - er32["u2"]) < 0.01
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kT", [1e-4, 1e-5, 1e-6])
+def test_storage_precision_128cube_shells_4_to_64(rf, ora, kT):
+    """The storage-precision study at 128^3 (200 steps, S(|n|) on shells
+    4..64), each precision paired with the FP64 oracle on the same noise."""
+    er64, er32, er16, erbf, dsk = precision_case(rf, ora, kT, (128, 128, 128), 200, (4, 64))
+    assert abs(er32["u2"] - er64["u2"]) < 1e-4
+    assert abs(er16["u2"] - er64["u2"]) < 1e-3
+    assert abs(erbf["u2"] - er64["u2"]) < 1e-2
+    assert dsk["f32"] < 1e-3
+    assert dsk["f16"] < 1e-2
+    for er in (er32, er16, erbf):
+        assert abs(er["u2"] - 1) < 0.01
+        assert abs(np.mean(er["sk_j"]) - 1) < 0.01
