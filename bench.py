@@ -344,9 +344,10 @@ def copy_ceiling(nbytes=4 << 30, reps=20):
     return 2 * nbytes / sec / 1e9
 
 
-def cpu_baseline(min_seconds=10.0, max_steps=10):
+def cpu_baseline(min_seconds=10.0, max_steps=200):
     """The FP64 oracle as it stands on the host cores, on a 128^3 sample of the
-    same workload (Taylor-Green, tau 0.6, kT 1e-5)."""
+    same workload (Taylor-Green, tau 0.6, kT 1e-5): whole steps until at least
+    min_seconds have passed."""
     import oracle
     import workloads as wl
 

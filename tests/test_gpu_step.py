@@ -70,6 +70,8 @@ CASES = {
     "rows_192x3x2_mrt": ((192, 3, 2), dict(kT=1e-4, tau=0.7, tau_bulk=0.9,
                                            tau_ghost=list(np.linspace(0.6, 1.9, 17)), seed=15)),
     "rows_1024x2x2": ((1024, 2, 2), dict(kT=1e-4, tau=0.8, seed=16)),
+    # a multiple of 64 beyond one block: odd steps fall back to tiles
+    "wide_1088x2x2": ((1088, 2, 2), dict(kT=1e-4, tau=0.65, seed=17)),
 }
 
 
