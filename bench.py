@@ -192,9 +192,11 @@ def table3_run(dims=(256, 256, 256), taus=TABLE3_TAUS, bgk_taus=(0.5005,) + TABL
             lat.step(burn)
             lat.stats_config(every)
             lat.reset_stats()
-            for _ in range(steps // sk_every):
+            for snap in range(steps // sk_every):
                 lat.step(sk_every)
                 lat.sk_sample()
+                if (snap + 1) % 10 == 0:
+                    log(f"table3 {model} tau={tau}: {(snap + 1) * sk_every} of {steps} steps")
             try:
                 lat.sync()
                 stable = True
@@ -383,6 +385,12 @@ def main():
     ap.add_argument("--table3", action="store_true",
                     help="equilibration ratios of Table III at 256^3, kT = 1/3000 (a physics "
                          "check against the paper, not a throughput figure)")
+    ap.add_argument("--table3-taus", metavar="T1,T2,...",
+                    help="with --table3: Reg-FLBM taus to run (default: every tau of Table III)")
+    ap.add_argument("--table3-bgk-taus", metavar="T1,T2,...",
+                    help="with --table3: BGK-FLBM taus to run ('' for none)")
+    ap.add_argument("--table3-steps", type=int, default=20000,
+                    help="with --table3: measured steps (400 statistics samples, 40 S(k) snapshots)")
     ap.add_argument("--summarize", metavar="DIR",
                     help="write profiles/ summaries from the rocprofv3 CSVs under DIR")
     ap.add_argument("--profile", action="store_true",
@@ -402,7 +410,13 @@ def main():
         profile_run(dims)
         return
     if args.table3:
-        print(json.dumps(table3_run()))
+        kw = {}
+        if args.table3_taus is not None:
+            kw["taus"] = tuple(float(t) for t in args.table3_taus.split(",") if t)
+        if args.table3_bgk_taus is not None:
+            kw["bgk_taus"] = tuple(float(t) for t in args.table3_bgk_taus.split(",") if t)
+        steps = args.table3_steps
+        print(json.dumps(table3_run(steps=steps, every=steps // 400, sk_every=steps // 40, **kw)))
         return
     main_run = run_gpu(dims, "f32", 1e-5, args.steps, args.warmup)
     n = dims[0] * dims[1] * dims[2]
