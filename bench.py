@@ -389,6 +389,8 @@ def main():
                     help="with --table3: Reg-FLBM taus to run (default: every tau of Table III)")
     ap.add_argument("--table3-bgk-taus", metavar="T1,T2,...",
                     help="with --table3: BGK-FLBM taus to run ('' for none)")
+    ap.add_argument("--table3-kT", type=float, default=1.0 / 3000.0,
+                    help="with --table3: temperature (the paper's 1/3000 by default)")
     ap.add_argument("--table3-steps", type=int, default=20000,
                     help="with --table3: measured steps (400 statistics samples, 40 S(k) snapshots)")
     ap.add_argument("--summarize", metavar="DIR",
@@ -416,7 +418,8 @@ def main():
         if args.table3_bgk_taus is not None:
             kw["bgk_taus"] = tuple(float(t) for t in args.table3_bgk_taus.split(",") if t)
         steps = args.table3_steps
-        print(json.dumps(table3_run(steps=steps, every=steps // 400, sk_every=steps // 40, **kw)))
+        print(json.dumps(table3_run(kT=args.table3_kT, steps=steps, every=steps // 400, sk_every=steps // 40,
+                                    **kw)))
         return
     main_run = run_gpu(dims, "f32", 1e-5, args.steps, args.warmup)
     n = dims[0] * dims[1] * dims[2]
