@@ -6,7 +6,7 @@ lets the oracle collide each source node with its own Philox noise (node
 index, step t), and compares population i of that post-collision state with
 what the GPU stored at y after the step, f_i(y, t + 1) = f*_i(y - c_i, t)
 (Eq. eq:streaming).  Two consecutive steps cover both AA parities.  Boxes:
-the 512^3 benchmark workload (FP32 and FP16 storage), a 1024^3 FP32 box
+the 512^3 benchmark workload (FP32, FP16 and BF16 storage), a 1024^3 FP32 box
 (116 GB, 2^30 nodes), and two replicas of the 64-replica batch.
 """
 import numpy as np
@@ -77,7 +77,7 @@ def check_one_step(lat, ora, p, dims, pts, storage="f32", sigma=None):
     return float(np.max(np.abs(q_got - q_ref) / allowed))
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_bench_workload_512cube_sampled(rf, ora, storage):
     dims = (512, 512, 512)
     print(f"[gpu] full size {dims} {storage}", flush=True)
