@@ -100,3 +100,16 @@ def test_conserved_modes_are_mass_and_momentum(ora):
     np.testing.assert_array_equal(t["e"][0], np.ones(27))
     for a in range(3):
         np.testing.assert_array_equal(t["e"][1 + a], t["c"][:, a])
+
+
+def test_table3_fixture_matches_benchmark_taus():
+    """The Table III fixture holds 14 taus, the ones the benchmark's Table III
+    mode runs, with BGK values from tau = 0.505 on (Sec. III)."""
+    import bench
+    paper = bench.paper_table3()
+    reg = sorted(t for m, t in paper if m == "reg")
+    bgk = sorted(t for m, t in paper if m == "bgk")
+    assert tuple(reg) == bench.TABLE3_TAUS
+    assert tuple(bgk) == bench.TABLE3_TAUS[3:]
+    assert paper[("reg", 0.5001)] == [1.037, 1.052, 1.072, 1.048]
+    assert paper[("bgk", 50.0)] == [0.953, 1.001, 0.930, 1.000]
