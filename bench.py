@@ -277,13 +277,13 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
     copy_bytes = 1 << 30
 
     def kind(name):
-        # FP32, Philox-10, no statistics: the even step is the tiled kernel, the
-        # odd step the whole-row kernel (or the tiled one when rows are off)
+        # FP32, Philox-10, no statistics: the even step is the one-wave kernel,
+        # the odd step the whole-row kernel (the tiled ones when rows are off)
         if "copy_kernel" in name:
             return "copy"
         if "step_row_kernel<0, 10>" in name or "step_kernel<0, true, 10, false>" in name:
             return "odd"
-        if "step_kernel<0, false, 10, false>" in name:
+        if "step_wave_kernel<0, 10>" in name or "step_kernel<0, false, 10, false>" in name:
             return "even"
         return None
 
@@ -323,7 +323,8 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
         fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
         fh.write("Name | Calls | AverageNs | MinNs | MaxNs\n")
         for r in stats:
-            if any(t in r["Name"] for t in ("step_kernel", "step_row_kernel", "copy_kernel", "init_eq_kernel")):
+            if any(t in r["Name"] for t in ("step_kernel", "step_row_kernel", "step_wave_kernel", "copy_kernel",
+                                            "init_eq_kernel")):
                 fh.write(f"{r['Name']} | {r['Calls']} | {float(r['AverageNs']):.0f} | "
                          f"{r['MinNs']} | {r['MaxNs']}\n")
         if dur:

@@ -187,8 +187,9 @@ void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStre
   L->stream = s;
   L->launch = make_launch(p.nx, p.ny, p.nz, p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64),
                           p.nx >= 256 ? 1 : (p.nx >= 128 ? 2 : 4));
-  // whole-row odd steps pay off where the step is bandwidth bound (FP32); the
-  // 16-bit steps are bound by arithmetic, where the lane moves cost more
+  // row-aligned blocks (whole-row odd steps, one-wave even steps) pay off where
+  // the step is bandwidth bound (FP32); the 16-bit steps are bound by
+  // arithmetic, where the lane moves of the odd step cost more than they save
   L->row_odd = p.storage == RFLBM_F32;
 }
 
@@ -278,6 +279,8 @@ rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps) {
     const bool odd = (t & 1) != 0;
     if (odd && !stats && L->row_odd && row_kernel_fits(L->p.nx))
       RFLBM_HIP(launch_step_row(L->p.storage, rounds, a, L->stream));
+    else if (!odd && !stats && L->row_odd && L->p.nx % 64 == 0)
+      RFLBM_HIP(launch_step_wave(L->p.storage, rounds, a, L->stream));
     else
       RFLBM_HIP(launch_step(L->p.storage, odd, rounds, stats, a, L->launch, L->stream));
     if (stats) RFLBM_HIP(launch_stats_reduce(a.partials, L->launch.grid, scratch, acc, L->stream));

@@ -94,6 +94,9 @@ Launch make_launch(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t bx, uint32_t 
 hipError_t launch_step(int storage, bool odd, int rounds, bool stats, const StepArgs& a,
                        const Launch& l, hipStream_t stream);
 
+// Even step without statistics in one-wave blocks (nx a multiple of 64).
+hipError_t launch_step_wave(int storage, int rounds, const StepArgs& a, hipStream_t stream);
+
 // True when the odd step can run in whole-row blocks: nx a multiple of 64, at
 // most 64 kMaxRowWaves.
 bool row_kernel_fits(uint32_t nx);

@@ -61,7 +61,9 @@ struct rflbm_lattice {
   int32_t stats_every = 0;
   rflbm::Launch launch{};
   bool xcd_remap = true;
-  bool row_odd = true;  // odd steps without statistics in whole-row blocks when nx fits (FP32 default)
+  // row-aligned blocks for steps without statistics (FP32 default): odd steps
+  // in whole-row blocks when nx fits, even steps in one-wave x-segments
+  bool row_odd = true;
   // S(k) state (library-allocated on first use)
   hipfftHandle plan = 0;
   bool have_plan = false;

@@ -222,6 +222,27 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
   }
 }
 
+// Even step without statistics in one-wave blocks: block b covers the 64
+// nodes x = 64 (b mod (nx / 64)) + lane of one x-row (nx a multiple of 64).
+template <int S, int ROUNDS>
+__global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
+  constexpr bool ODD = false, STATS = false, SMALL_BOX = false, ROW_SHIFT = false, BUFFER_ACCESS = true;
+  [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
+  [[maybe_unused]] const uint32_t tid = 0;
+  [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
+  [[maybe_unused]] uint32_t (*row_edge_out)[kMaxRowWaves] = nullptr;
+  uint32_t seg = blockIdx.x;
+  if (a.xcd_remap) seg = (seg & 7u) * (gridDim.x >> 3) + (seg >> 3);
+  const uint32_t per_row = a.nx >> 6;
+  const uint32_t row = seg / per_row;
+  if (row >= a.ny * a.nz) return;  // the whole block: rounding of the grid to 8
+  const uint32_t x = (seg - row * per_row) * 64 + threadIdx.x;
+  const uint32_t y = row % a.ny;
+  const uint32_t z = row / a.ny;
+  const uint32_t step = a.step;
+#include "node_body.inc"
+}
+
 // Odd step of one box in whole-row blocks: block b covers the x-row (y, z) of
 // row index y + ny z (blockDim.x = nx, a multiple of 64 up to 1024), so that
 // the +-1 shifts in x stay inside the block and every load and store is a
@@ -376,7 +397,31 @@ hipError_t launch_row_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_
   return hipGetLastError();
 }
 
+template <int S>
+hipError_t launch_wave_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_t s) {
+  switch (rounds) {
+    case 0: hipLaunchKernelGGL((step_wave_kernel<S, 0>), dim3(grid), dim3(64), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((step_wave_kernel<S, 7>), dim3(grid), dim3(64), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((step_wave_kernel<S, 10>), dim3(grid), dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_step_wave(int storage, int rounds, const StepArgs& a, hipStream_t stream) {
+  if (a.nx % 64 != 0 || a.nx == 0) return hipErrorInvalidConfiguration;
+  const uint64_t segs = static_cast<uint64_t>(a.nx / 64) * a.ny * a.nz;
+  if (segs >= (1ull << 31)) return hipErrorInvalidConfiguration;
+  const uint32_t grid = static_cast<uint32_t>((segs + 7) / 8 * 8);
+  switch (storage) {
+    case kF32: return launch_wave_s<kF32>(rounds, a, grid, stream);
+    case kF16: return launch_wave_s<kF16>(rounds, a, grid, stream);
+    case kBF16: return launch_wave_s<kBF16>(rounds, a, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 bool row_kernel_fits(uint32_t nx) { return nx % 64 == 0 && nx >= 64 && nx <= kMaxRowWaves * 64; }
 
