@@ -123,6 +123,51 @@ def precision_study(dims=(128, 128, 128), kts=(1e-4, 1e-5, 1e-6), steps=400, eve
     return out
 
 
+def precision_full(dims=(512, 512, 512), kts=(1e-4, 1e-5, 1e-6), steps=1000, every=10, sk_every=100):
+    """The storage-precision form on the benchmark workload: thermal
+    fluctuations on the Taylor-Green flow (A = 0.01), tau = 0.6, ghosts at 1,
+    the same seed (the same noise) for FP32, FP16 and BF16 storage.  Per kT:
+    <u^2> (flow plus fluctuations) and the momentum S(|n|) / (3 rho0 kT) on
+    shells 4..64 (away from the Taylor-Green modes), and the 16-bit storages'
+    differences from FP32."""
+    import numpy as np
+    import torch
+
+    import paper_2507_08820_amd as rf
+    import workloads as wl
+
+    out = {}
+    for kT in kts:
+        res = {}
+        for storage in ("f32", "f16", "bf16"):
+            lat = rf.Lattice(dims, storage=storage, kT=kT, tau=0.6, tau_bulk=0.6, tau_ghost=1.0, seed=3)
+            rho, u = wl.taylor_green_device(dims, amp=0.01, device=lat.device)
+            lat.init_thermal(rho, u)
+            del rho, u
+            lat.stats_config(every)
+            for _ in range(steps // sk_every):
+                lat.sk_sample()
+                lat.step(sk_every)
+            st = lat.stats()
+            n = st["samples"] * st["nodes"]
+            js = sum(lat.sk(f)[0] for f in ("jx", "jy", "jz"))
+            _, counts, ns = lat.sk("jx")
+            lat.sync()
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+            res[storage] = dict(u2=float(np.sum(st["sum_u2"]) / n),
+                                sk=js[4:65] / counts[4:65] / ns / (3 * kT))
+        row = {"u2_f32": res["f32"]["u2"], "sk_mean_f32": float(np.mean(res["f32"]["sk"]))}
+        for s16 in ("f16", "bf16"):
+            row[f"u2_rel_diff_{s16}"] = (res[s16]["u2"] - res["f32"]["u2"]) / res["f32"]["u2"]
+            row[f"sk_max_abs_diff_{s16}"] = float(np.max(np.abs(res[s16]["sk"] - res["f32"]["sk"])))
+        out[f"kT={kT:g}"] = {k: float(f"{v:.6g}") for k, v in row.items()}
+        log(f"precision 512^3 kT={kT:g}: {out[f'kT={kT:g}']}")
+    return {"box": list(dims), "steps": steps, "stats_every": every, "sk_every": sk_every,
+            "start": "thermal fluctuations on Taylor-Green A=0.01", "rows": out}
+
+
 def run_batch(storage, steps=200, graph_steps=20):
     """The 64-replica workload: boxes 32^3..96^3, tau in [0.55, 1.2], kT in
     [1e-6, 1e-4], Taylor-Green A = 0.01 per box; aggregate MLUPS of the
@@ -412,6 +457,9 @@ def main():
                     help="with --table3: temperature (the paper's 1/3000 by default)")
     ap.add_argument("--table3-steps", type=int, default=20000,
                     help="with --table3: measured steps (400 statistics samples, 40 S(k) snapshots)")
+    ap.add_argument("--precision512", action="store_true",
+                    help="storage precision on the 512^3 workload: FP16 and BF16 against FP32 with "
+                         "the same noise, kT in {1e-4, 1e-5, 1e-6}, 1000 steps")
     ap.add_argument("--summarize", metavar="DIR",
                     help="write profiles/ summaries from the rocprofv3 CSVs under DIR")
     ap.add_argument("--profile", action="store_true",
@@ -429,6 +477,9 @@ def main():
         return
     if args.profile:
         profile_run(dims)
+        return
+    if args.precision512:
+        print(json.dumps(precision_full()))
         return
     if args.table3:
         kw = {}
