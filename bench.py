@@ -89,8 +89,8 @@ def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0):
     torch.cuda.empty_cache()
     n = dims[0] * dims[1] * dims[2]
     r = dict(ms=ms, wall_s=wall, mlups=n * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps)
-    log(f"{dims} {storage} kT={kT}: {steps} steps, {r['ms_per_step']:.4f} ms/step, "
-        f"{r['mlups']:.0f} MLUPS")
+    log(f"{dims} {storage} kT={kT}{f' stats every {stats_every}' if stats_every else ''}: {steps} steps, "
+        f"{r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS")
     return r
 
 
@@ -506,6 +506,8 @@ def main():
             r = run_gpu(dims, storage, kT, short, 5)
             extra[name] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                            "hbm_gbs": round(BYTES_PER_UPDATE[storage] * n / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
+        r = run_gpu(dims, "f32", 1e-5, short, 5, stats_every=1)
+        extra["f32_stats_every_step"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4)}
         extra["f16_gain_over_f32"] = round(extra["f16_store"]["mlups"] / main_run["mlups"], 3)
         extra["noise_cost_factor"] = round(extra["reg_lbm_kT0_f32"]["mlups"] / main_run["mlups"], 3)
         extra["u2_over_kT_by_storage_128cube"] = precision_study()
