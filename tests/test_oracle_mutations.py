@@ -1,0 +1,68 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's C source (on the CPU,
+in a scratch directory; the GPU path is not involved), rebuilds that copy and
+runs the oracle's pin tests against it: at least one pin must fail.  The
+mistakes are the kind a transcription of Table II, Eq. normal_fact,
+Eq. fluct_phi, Eq. r-flbe2 or Eq. eq:streaming could contain.  The unmutated
+copy must pass, so a failure is the mistake's doing and not the harness's.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PIN_TESTS = ["tests/test_oracle_tables.py", "tests/test_oracle_collide.py", "tests/test_oracle_dynamics.py"]
+
+# (name, text in rflbm_oracle.c, replacement)
+MUTATIONS = [
+    ("none", None, None),
+    ("multiplicity_mu7", "{1, 1, 1, 1, 1, 1, 1, 2, 2, 2,", "{1, 1, 1, 1, 1, 1, 1, 1, 2, 2,"),
+    ("table2_typo_mode13", "case 13: return x * z * z - s * x;", "case 13: return x * z * z - s * z;"),
+    ("cs2_in_Hxx", "case 4: return x * x - s;", "case 4: return x * x - 0.5 * s;"),
+    ("hermite_index_mode16", '"yyz",   "xyz",', '"yyz",   "xzz",'),
+    ("fdt_omega_1_minus_omega", "sqrt(omega * (2.0 - omega))", "sqrt(omega * (1.0 - omega))"),
+    ("ghost_noise_b_inverse", "sqrt(mu * B[k]) * fdt_factor(om_g)", "sqrt(mu / B[k]) * fdt_factor(om_g)"),
+    ("ghost_relaxation_sign", "relaxed[k] = (1.0 - om_g) * a1[k];", "relaxed[k] = (om_g - 1.0) * a1[k];"),
+    ("trace_over_two", "(a1[4] + a1[5] + a1[6]) / 3.0;", "(a1[4] + a1[5] + a1[6]) / 2.0;"),
+    ("bulk_shear_noise_swapped",
+     "(fdt_factor(om_b) * r_mean + fdt_factor(om_s) * (r[k - 4] - r_mean))",
+     "(fdt_factor(om_s) * r_mean + fdt_factor(om_b) * (r[k - 4] - r_mean))"),
+    ("reference_density_in_phi", "const double mu = rho * p->kT / CS2;", "const double mu = p->rho0 * p->kT / CS2;"),
+    ("streaming_direction", "const int32_t xd = (x + C[i][0] + nx) % nx;", "const int32_t xd = (x - C[i][0] + nx) % nx;"),
+]
+
+
+def make_copy(dst, old, new):
+    os.makedirs(os.path.join(dst, "oracle"))
+    for name in ("__init__.py", "rflbm_oracle.c"):
+        shutil.copy(os.path.join(ROOT, "oracle", name), os.path.join(dst, "oracle", name))
+    shutil.copytree(os.path.join(ROOT, "tests"), os.path.join(dst, "tests"),
+                    ignore=shutil.ignore_patterns("__pycache__", "test_gpu_*", "test_oracle_mutations.py"))
+    for name in ("workloads.py", "pytest.ini", "bench.py"):
+        shutil.copy(os.path.join(ROOT, name), os.path.join(dst, name))
+    if old is not None:
+        path = os.path.join(dst, "oracle", "rflbm_oracle.c")
+        with open(path) as fh:
+            src = fh.read()
+        assert src.count(old) == 1, old
+        with open(path, "w") as fh:
+            fh.write(src.replace(old, new))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_fails_a_pin(tmp_path, name, old, new):
+    dst = str(tmp_path / "copy")
+    make_copy(dst, old, new)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "-m", "not gpu and not slow"] + PIN_TESTS,
+                       cwd=dst, capture_output=True, text=True, timeout=900)
+    tail = (r.stdout + r.stderr)[-1500:]
+    if old is None:
+        assert r.returncode == 0, tail
+    else:
+        assert r.returncode == 1, tail  # 1: tests ran and at least one failed
