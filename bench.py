@@ -291,6 +291,44 @@ def table3_run(dims=(256, 256, 256), taus=TABLE3_TAUS, bgk_taus=(0.5005,) + TABL
             "sk_every": sk_every, "rows": rows}
 
 
+VALU_CMD = ("rocprofv3 --pmc VALUBusy SQ_INSTS_VALU -d <out>/prof_valu_{s} -o valu --output-format csv "
+            "-- python3 bench.py --profile --profile-storage {s}")
+
+
+def summarize_valu(out_dir, storage, dims=(512, 512, 512)):
+    """profiles/step_<storage>_512_valu.txt: per step kernel, the mean over its
+    dispatches of VALUBusy (percent of GPU time the vector ALUs issue) and of
+    the VALU instructions per node (SQ_INSTS_VALU counts wave instructions)."""
+    import csv
+    import glob
+    import re
+
+    files = glob.glob(os.path.join(out_dir, f"prof_valu_{storage}", "*counter_collection.csv"))
+    if not files:
+        raise FileNotFoundError(f"prof_valu_{storage}")
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    n = dims[0] * dims[1] * dims[2]
+    acc = {}
+    for r in rows:
+        m = re.search(r"(step_\w*kernel<[^>]*>)", r["Kernel_Name"])
+        if not m:
+            continue
+        short = m.group(1)
+        acc.setdefault(short, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    path = os.path.join(ROOT, "profiles", f"step_{storage}_512_valu.txt")
+    with open(path, "w") as fh:
+        fh.write(f"# VALU activity of the step kernels, 512^3 {storage.upper()} bench workload (4 timed + 2 warm-up steps)\n")
+        fh.write(f"# command: {VALU_CMD.format(s=storage)}\n")
+        fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
+        fh.write("kernel | dispatches | VALUBusy % | VALU instructions per node\n")
+        for k, c in sorted(acc.items()):
+            busy = sum(c.get("VALUBusy", [0.0])) / max(1, len(c.get("VALUBusy", [])))
+            insts = c.get("SQ_INSTS_VALU", [0.0])
+            fh.write(f"{k} | {len(insts)} | {busy:.1f} | {sum(insts) / len(insts) * 64 / n:.0f}\n")
+    return path
+
+
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -d <out>/prof_trace -o trace --output-format csv "
              "-- python3 bench.py --steps 60 --warmup 10 --no-extra --no-cpu-baseline",
@@ -380,12 +418,12 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
     return traffic, dur
 
 
-def profile_run(dims):
+def profile_run(dims, storage="f32"):
     import torch
 
     import paper_2507_08820_amd as rf
 
-    run_gpu(dims, "f32", 1e-5, 4, 2)
+    run_gpu(dims, storage, 1e-5, 4, 2)
     nbytes = 1 << 30
     src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -457,6 +495,10 @@ def main():
                     help="with --table3: temperature (the paper's 1/3000 by default)")
     ap.add_argument("--table3-steps", type=int, default=20000,
                     help="with --table3: measured steps (400 statistics samples, 40 S(k) snapshots)")
+    ap.add_argument("--profile-storage", default="f32", choices=["f32", "f16", "bf16"],
+                    help="with --profile: storage of the profiled workload")
+    ap.add_argument("--summarize-valu", metavar="DIR",
+                    help="write profiles/step_<storage>_512_valu.txt from the VALU counter CSVs under DIR")
     ap.add_argument("--precision512", action="store_true",
                     help="storage precision on the 512^3 workload: FP16 and BF16 against FP32 with "
                          "the same noise, kT in {1e-4, 1e-5, 1e-6}, 1000 steps")
@@ -476,7 +518,11 @@ def main():
         print(summarize_profiles(args.summarize))
         return
     if args.profile:
-        profile_run(dims)
+        profile_run(dims, args.profile_storage)
+        return
+    if args.summarize_valu:
+        for storage in ("f32", "f16"):
+            print(summarize_valu(args.summarize_valu, storage))
         return
     if args.precision512:
         print(json.dumps(precision_full()))
