@@ -64,7 +64,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0):
+def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0, followups=()):
+    """Times `steps` steps of one lattice after `warmup` steps.  Each follow-up
+    (label, kT, stats_every, steps) is then timed on the same lattice (the same
+    placement in HBM, so the comparison with the main figure is fair)."""
     import torch
 
     import paper_2507_08820_amd as rf
@@ -84,13 +87,21 @@ def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat.sync()
+    n = dims[0] * dims[1] * dims[2]
+    r = dict(ms=ms, wall_s=wall, mlups=n * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps, followups={})
+    log(f"{dims} {storage} kT={kT}{f' stats every {stats_every}' if stats_every else ''}: {steps} steps, "
+        f"{r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS")
+    for label, f_kT, f_stats, f_steps in followups:
+        lat.set_params(**dict(kw, kT=f_kT))
+        lat.stats_config(f_stats)
+        lat.step(2)
+        f_ms = lat.time_steps(f_steps)
+        lat.sync()
+        r["followups"][label] = dict(ms_per_step=f_ms / f_steps, mlups=n * f_steps / (f_ms * 1e-3) / 1e6)
+        log(f"  same lattice, {label}: {f_ms / f_steps:.4f} ms/step, {r['followups'][label]['mlups']:.0f} MLUPS")
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    n = dims[0] * dims[1] * dims[2]
-    r = dict(ms=ms, wall_s=wall, mlups=n * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps)
-    log(f"{dims} {storage} kT={kT}{f' stats every {stats_every}' if stats_every else ''}: {steps} steps, "
-        f"{r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS")
     return r
 
 
@@ -537,7 +548,9 @@ def main():
         print(json.dumps(table3_run(kT=args.table3_kT, steps=steps, every=steps // 400, sk_every=steps // 40,
                                     **kw)))
         return
-    main_run = run_gpu(dims, "f32", 1e-5, args.steps, args.warmup)
+    short = max(20, args.steps // 4)
+    followups = () if args.no_extra else (("stats_every_step", 1e-5, 1, short), ("kT0_reg_lbm", 0.0, 0, short))
+    main_run = run_gpu(dims, "f32", 1e-5, args.steps, args.warmup, followups=followups)
     n = dims[0] * dims[1] * dims[2]
     achieved = BYTES_PER_UPDATE["f32"] * n / (main_run["ms_per_step"] * 1e-3) / 1e9
     traffic = measured_traffic() if dims == (512, 512, 512) else None
@@ -546,16 +559,17 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        short = max(20, args.steps // 4)
-        for name, storage, kT in (("f16_store", "f16", 1e-5), ("bf16_store", "bf16", 1e-5),
-                                  ("reg_lbm_kT0_f32", "f32", 0.0)):
-            r = run_gpu(dims, storage, kT, short, 5)
+        for name, storage in (("f16_store", "f16"), ("bf16_store", "bf16")):
+            r = run_gpu(dims, storage, 1e-5, short, 5)
             extra[name] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                            "hbm_gbs": round(BYTES_PER_UPDATE[storage] * n / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
-        r = run_gpu(dims, "f32", 1e-5, short, 5, stats_every=1)
-        extra["f32_stats_every_step"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4)}
+        # same lattice as the main figure
+        for name, label in (("f32_stats_every_step", "stats_every_step"), ("reg_lbm_kT0_f32", "kT0_reg_lbm")):
+            f = main_run["followups"][label]
+            extra[name] = {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["ms_per_step"], 4)}
         extra["f16_gain_over_f32"] = round(extra["f16_store"]["mlups"] / main_run["mlups"], 3)
         extra["noise_cost_factor"] = round(extra["reg_lbm_kT0_f32"]["mlups"] / main_run["mlups"], 3)
+        extra["stats_cost_factor"] = round(extra["f32_stats_every_step"]["mlups"] / main_run["mlups"], 3)
         extra["u2_over_kT_by_storage_128cube"] = precision_study()
         extra["batch64_f32"] = run_batch("f32")
         extra["batch64_f16"] = run_batch("f16")
