@@ -4,7 +4,8 @@
   <d rho^2> = rho0 kT / cs2, <d Pi_aa^2> = mu b_4, <d Pi_ab^2> = mu b_7, each
   within 1 %, and S(|n|) flat per shell (16^3, tau = 1, kT = 1e-4);
 - shear-wave decay at nu = cs2 (tau - 1/2) with thermal noise on (128^3,
-  tau_s = 0.8, tau_b = 1, kT = 1e-5);
+  tau_s = 0.8, tau_b = 1, kT = 1e-5), and the noise statistics of the
+  directions the wave does not touch (<u_y^2>, <u_z^2>, <d rho^2>);
 - storage precision: FP16 and BF16 deviation storage against FP32 and against
   the FP64 oracle run with the same noise, kT in {1e-4, 1e-5, 1e-6}: <u^2>,
   <d rho^2> and the momentum S(|n|) at 32^3 (shells 1..15) and at 128^3
@@ -74,6 +75,8 @@ def test_shear_wave_decay_with_noise_128cube(rf):
     s = np.sin(2 * np.pi * z / L)
     amps, ts = [], []
     for k in range(51):
+        if k == 10:
+            lat.stats_config(10)  # noise statistics over steps 1000..5000
         j = lat.moments(rf.M_RHO | rf.M_J).double().cpu().numpy()
         ux = (j[1] / j[0]).reshape(L, L, L).mean(axis=(1, 2))
         amps.append(2 * np.mean(ux * s))
@@ -82,10 +85,22 @@ def test_shear_wave_decay_with_noise_128cube(rf):
             lat.step(100)
     rate = -np.polyfit(ts[5:], np.log(amps[5:]), 1)[0]
     nu_k2 = CS2 * (tau - 0.5) * (2 * np.pi / L) ** 2
+    # the noise in the directions the wave does not touch: <u_y^2>, <u_z^2> =
+    # kT / rho0 and <d rho^2> = rho0 kT / cs2 (equilibrated from the noise-free
+    # start by step 1000 except for a few dozen of the 2 M modes)
+    st = lat.stats()
+    n = st["samples"] * st["nodes"]
+    er_uy = st["sum_u2"][1] / n / 1e-5
+    er_uz = st["sum_u2"][2] / n / 1e-5
+    er_rho = (st["sum_drho2"] / n - (st["sum_drho"] / n) ** 2) / (1e-5 / CS2)
     print(f"[gpu] shear decay rate {rate:.6e} vs nu k^2 {nu_k2:.6e}; "
-          f"A(5000)/A(0) = {amps[-1] / amps[0]:.4f}", flush=True)
+          f"A(5000)/A(0) = {amps[-1] / amps[0]:.4f}; ER(u_y^2) {er_uy:.4f} ER(u_z^2) {er_uz:.4f} "
+          f"ER(d rho^2) {er_rho:.4f} over {st['samples']} samples", flush=True)
     assert abs(rate / nu_k2 - 1) < 0.005
     assert abs(amps[-1] / amps[0] - np.exp(-nu_k2 * 5000)) < 0.005
+    assert st["samples"] == 400
+    for er in (er_uy, er_uz, er_rho):
+        assert abs(er - 1) < 0.01
     lat.sync()
 
 
