@@ -72,6 +72,11 @@ CASES = {
     "rows_1024x2x2": ((1024, 2, 2), dict(kT=1e-4, tau=0.8, seed=16)),
     # a multiple of 64 beyond one block: odd steps fall back to tiles
     "wide_1088x2x2": ((1088, 2, 2), dict(kT=1e-4, tau=0.65, seed=17)),
+    # the row-aligned kernels without noise, with the BGK model, with Philox-7
+    "rows_kT0_128x4x3": ((128, 4, 3), dict(kT=0.0, tau=0.55)),
+    "rows_bgk_64x6x5": ((64, 6, 5), dict(kT=1e-4, tau=0.8, model="bgk", seed=18)),
+    "rows_philox7_256x2x3": ((256, 2, 3), dict(kT=1e-4, tau=0.9, philox_rounds=7, seed=(3 << 32) + 19,
+                                                stream_id=5)),
 }
 
 
