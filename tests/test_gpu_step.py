@@ -131,6 +131,26 @@ def test_row_blocks_match_tiled_bitwise(rf, ora, dims, storage):
         lat.sync()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_statistics_steps_store_the_same_populations(rf, ora, storage):
+    """Steps that accumulate statistics (their own kernel variant) leave the
+    same bits in the populations as steps that do not."""
+    dims = (128, 5, 6)
+    f = initial_state(ora, dims, seed=31)
+    lats = []
+    for every in (1, 0):
+        lat = rf.Lattice(dims, storage=storage, kT=1e-4, tau=0.7, seed=6)
+        lat.set_populations(f)
+        lat.stats_config(every)
+        lat.step(7)
+        lats.append(lat)
+    a, b = (lat.populations() for lat in lats)
+    assert bool((a == b).all())
+    assert lats[0].stats()["samples"] == 7 and lats[1].stats()["samples"] == 0
+    for lat in lats:
+        lat.sync()
+
+
 def test_rng_matches_oracle(rf, ora):
     for seed, sid, rounds, node0, count, t in [(1, 0, 10, 0, 4096, 0),
                                                ((5 << 32) + 7, 3, 10, 123456, 2048, 2 ** 31 + 5),
