@@ -18,6 +18,13 @@
 //   7. transform back (Eq. backtrasf) and scatter the 27 post-collision
 //      values to their AA destination slots.
 // Everything between the 27 loads and the 27 stores stays in registers.
+//
+// The same body runs in four kernels: step_kernel (tiles of 256 nodes of one z
+// plane; every step shape, statistics included), step_wave_kernel (even steps
+// in one-wave x-segments), step_row_kernel (odd steps in whole x-rows, where
+// values move between lanes so that every access covers whole cache lines)
+// and batch_kernel (many boxes, persistent grid over tiles of consecutive
+// nodes).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
