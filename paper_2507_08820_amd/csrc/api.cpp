@@ -174,6 +174,9 @@ StepArgs step_args(const rflbm_lattice* L) {
     a.lam_g[k - 10] = static_cast<float>(1.0 - om_g);
     a.amp_g[k - 10] = static_cast<float>(std::sqrt(kt * mode_norm(k) / kCs2) * fdt(om_g));
   }
+  a.ghost_eq = 1;
+  for (int k = 0; k < 17; ++k)
+    if (a.lam_g[k] != 0.0f) a.ghost_eq = 0;
   sigma_of(p, a.sigma, a.inv_sigma);
   a.flag = reinterpret_cast<int*>(L->buf + L->L.flag_off);
   a.partials = reinterpret_cast<double*>(L->buf + L->L.partial_off);

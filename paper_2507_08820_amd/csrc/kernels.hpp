@@ -49,6 +49,7 @@ struct StepArgs {
   float amp_s;           // sqrt(kT b_4 / cs2) s(omega_s), s(w) = sqrt(w (2 - w)); modes 4..6
   float amp_b_minus_s;   // sqrt(kT b_4 / cs2) (s(omega_b) - s(omega_s))
   float amp_off;         // sqrt(kT b_7 / cs2) s(omega_s), modes 7..9
+  uint32_t ghost_eq;     // 1 when every omega_g,k = 1 (all lam_g = 0)
   float lam_g[17];       // 1 - omega_g,k, k = 10..26
   float amp_g[17];       // sqrt(kT b_k / cs2) s(omega_g,k)
   float sigma[4];        // storage unit per speed class (1 for FP32)
