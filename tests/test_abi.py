@@ -103,6 +103,10 @@ def test_null_arguments():
     assert lib.rflbm_step(None, 1) == _binding.EINVAL
     assert lib.rflbm_step_count(None) == -1
     assert lib.rflbm_destroy(None) == _binding.OK
+    assert lib.rflbm_set_row_blocks(None, 1) == _binding.EINVAL
+    active = ctypes.c_int32(7)
+    assert lib.rflbm_get_row_blocks(None, ctypes.byref(active)) == _binding.EINVAL
+    assert active.value == 7
 
 
 def test_batch_validation():
