@@ -158,7 +158,8 @@ rflbm_status rflbm_set_step_count(rflbm_lattice* lat, int64_t t);
 rflbm_status rflbm_get_populations(rflbm_lattice* lat, double* dst, int dst_is_host);
 /* Reads f(x, t) at `count` nodes only: nodes[k] (device array of node indices
  * n < N) -> dst[i * count + k] (device, FP64, 27 * count values).  For
- * checking large boxes against a reference one node at a time. */
+ * checking large boxes against a reference one node at a time.  An index
+ * n >= N reads nothing and yields NaN for its 27 values. */
 rflbm_status rflbm_get_populations_at(rflbm_lattice* lat, const uint32_t* nodes, uint32_t count,
                                       double* dst);
 /* Writes the populations f(x, t) from src (FP64, planar, 27 N values); clears

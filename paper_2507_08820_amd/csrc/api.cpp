@@ -561,16 +561,24 @@ static rflbm_status sk_prepare(rflbm_lattice* L) {
   const uint64_t N = nodes(L);
   L->nshells = rflbm_sk_nshells(L);
   const size_t spec_bytes = static_cast<size_t>(L->p.nx / 2 + 1) * L->p.ny * L->p.nz * 2 * sizeof(float);
-  RFLBM_HIP(hipMalloc(reinterpret_cast<void**>(&L->sk_fields), 10 * N * sizeof(float)));
-  RFLBM_HIP(hipMalloc(&L->sk_spec, spec_bytes));
-  RFLBM_HIP(hipMalloc(reinterpret_cast<void**>(&L->sk_sums), 10 * L->nshells * sizeof(double)));
-  RFLBM_HIP(hipMalloc(reinterpret_cast<void**>(&L->sk_counts), L->nshells * sizeof(unsigned long long)));
+  // buffers that an earlier, failed attempt allocated are kept and reused
+  if (!L->sk_fields) RFLBM_HIP(hipMalloc(reinterpret_cast<void**>(&L->sk_fields), 10 * N * sizeof(float)));
+  if (!L->sk_spec) RFLBM_HIP(hipMalloc(&L->sk_spec, spec_bytes));
+  if (!L->sk_sums) RFLBM_HIP(hipMalloc(reinterpret_cast<void**>(&L->sk_sums), 10 * L->nshells * sizeof(double)));
+  if (!L->sk_counts)
+    RFLBM_HIP(hipMalloc(reinterpret_cast<void**>(&L->sk_counts), L->nshells * sizeof(unsigned long long)));
   RFLBM_HIP(hipMemsetAsync(L->sk_sums, 0, 10 * L->nshells * sizeof(double), L->stream));
   RFLBM_HIP(hipMemsetAsync(L->sk_counts, 0, L->nshells * sizeof(unsigned long long), L->stream));
-  if (hipfftPlan3d(&L->plan, L->p.nz, L->p.ny, L->p.nx, HIPFFT_R2C) != HIPFFT_SUCCESS)
+  hipfftHandle plan;
+  if (hipfftPlan3d(&plan, L->p.nz, L->p.ny, L->p.nx, HIPFFT_R2C) != HIPFFT_SUCCESS)
     return fail(RFLBM_EHIP, "hipfftPlan3d failed");
+  // the plan is kept only once it runs on the lattice stream
+  if (hipfftSetStream(plan, L->stream) != HIPFFT_SUCCESS) {
+    (void)hipfftDestroy(plan);
+    return fail(RFLBM_EHIP, "hipfftSetStream failed");
+  }
+  L->plan = plan;
   L->have_plan = true;
-  if (hipfftSetStream(L->plan, L->stream) != HIPFFT_SUCCESS) return fail(RFLBM_EHIP, "hipfftSetStream failed");
   L->sk_samples = 0;
   return RFLBM_OK;
 }

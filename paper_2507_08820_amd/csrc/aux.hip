@@ -69,7 +69,14 @@ __global__ void get_pop_at_kernel(const GatherArgs g, const uint32_t* nodes, uin
   const T* pop = static_cast<const T*>(g.pop);
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= count) return;
-  const NodeXYZ p = coords(nodes[k], g.nx, g.ny);
+  const uint32_t n = nodes[k];
+  if (static_cast<uint64_t>(n) >= static_cast<uint64_t>(g.nx) * g.ny * g.nz) {
+    // not a node of the box: nothing is read, the 27 values are NaN
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) dst[static_cast<uint64_t>(i) * count + k] = __builtin_nan("");
+    return;
+  }
+  const NodeXYZ p = coords(n, g.nx, g.ny);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const int cls = speed_class(i);

@@ -360,3 +360,31 @@ def test_thermal_start_matches_oracle(rf, ora, storage):
         q_want, q_got = (want - 1.2 * w) / sigma, (got - 1.2 * w) / sigma
         allowed = 0.5 * ulp16(q_want, storage) * 1.001 + 2e-6 * (1 + np.abs(q_want))
         assert np.all(np.abs(q_got - q_want) <= allowed)
+
+
+def test_populations_at_outside_the_box_reads_nothing(rf, ora):
+    """Through the C interface, an index n >= N yields NaN and reads no memory;
+    indices inside the box give the values of the full readback."""
+    import ctypes
+
+    import torch
+    from paper_2507_08820_amd import _binding
+
+    dims = (8, 6, 5)
+    n = 8 * 6 * 5
+    lat = rf.Lattice(dims, kT=1e-4, tau=0.8, seed=5)
+    lat.set_populations(initial_state(ora, dims, seed=81))
+    lat.step(3)
+    full = lat.populations().cpu().numpy()
+    idx = torch.as_tensor(np.array([0, n - 1, n, n + 7, 2**32 - 1, 17], dtype=np.uint32), device=lat.device)
+    out = torch.empty((27, idx.numel()), dtype=torch.float64, device=lat.device)
+    st = lat.lib.rflbm_get_populations_at(lat._h, _binding._VP(idx.data_ptr()), idx.numel(),
+                                          _binding._VP(out.data_ptr()))
+    assert st == _binding.OK
+    lat.sync()
+    got = out.cpu().numpy()
+    np.testing.assert_array_equal(got[:, [0, 1, 5]], full[:, [0, n - 1, 17]])
+    assert np.all(np.isnan(got[:, 2:5]))
+    with pytest.raises(ValueError):
+        lat.populations_at([n])
+    lat.close()
