@@ -177,6 +177,22 @@ def _dev_ptr(t) -> int:
     return int(t.data_ptr())
 
 
+def _after_torch(stream, device):
+    """Orders `stream` after the work torch has queued on its current stream
+    (inputs it just copied, memory its caching allocator just handed out)."""
+    cur = _torch().cuda.current_stream(device)
+    if cur != stream:
+        stream.wait_stream(cur)
+
+
+def _before_torch(stream, device):
+    """Orders torch's current stream after the work queued on `stream` (results
+    the library wrote into tensors that torch code reads next)."""
+    cur = _torch().cuda.current_stream(device)
+    if cur != stream:
+        cur.wait_stream(stream)
+
+
 def _as_device_f64(a, device):
     torch = _torch()
     if isinstance(a, torch.Tensor):
@@ -205,6 +221,7 @@ class Lattice:
         self._ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = _VP()
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_create(ctypes.byref(self.params), _VP(self._ptr), nbytes,
                                     _VP(self.stream.cuda_stream), ctypes.byref(self._h)))
 
@@ -261,6 +278,7 @@ class Lattice:
                                                      if not hasattr(rho, "data_ptr") else rho,
                                                      self.device)
         v = None if u is None else _as_device_f64(u, self.device).reshape(3, self.n)
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_init_equilibrium(self._h, None if r is None else _VP(_dev_ptr(r)),
                                               None if v is None else _VP(_dev_ptr(v)), 0))
         self._keep = (r, v)  # alive until the stream has consumed them
@@ -272,6 +290,7 @@ class Lattice:
                                                      if not hasattr(rho, "data_ptr") else rho,
                                                      self.device)
         v = None if u is None else _as_device_f64(u, self.device).reshape(3, self.n)
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_init_thermal(self._h, None if r is None else _VP(_dev_ptr(r)),
                                           None if v is None else _VP(_dev_ptr(v)), 0))
         self._keep = (r, v)
@@ -281,7 +300,9 @@ class Lattice:
         """f(x, t) as a (27, N) float64 tensor on the device."""
         torch = _torch()
         out = torch.empty((27, self.n), dtype=torch.float64, device=self.device)
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_get_populations(self._h, _VP(_dev_ptr(out)), 0))
+        _before_torch(self.stream, self.device)
         return out
 
     def populations_at(self, nodes):
@@ -293,6 +314,7 @@ class Lattice:
             raise ValueError("node index outside the box")
         nd = torch.as_tensor(idx.astype(np.uint32), device=self.device)
         out = torch.empty((27, idx.size), dtype=torch.float64, device=self.device)
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_get_populations_at(self._h, _VP(_dev_ptr(nd)), int(idx.size),
                                                 _VP(_dev_ptr(out))))
         self.stream.synchronize()
@@ -300,6 +322,7 @@ class Lattice:
 
     def set_populations(self, f):
         d = _as_device_f64(f, self.device).reshape(27, self.n)
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_set_populations(self._h, _VP(_dev_ptr(d)), 0))
         self.stream.synchronize()
 
@@ -307,7 +330,9 @@ class Lattice:
         torch = _torch()
         nf = (1 if mask & M_RHO else 0) + (3 if mask & M_J else 0) + (6 if mask & M_PI else 0)
         out = torch.empty((nf, self.n), dtype=torch.float32, device=self.device)
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_get_moments(self._h, mask, _VP(_dev_ptr(out)), 0))
+        _before_torch(self.stream, self.device)
         return out
 
     # -- stepping --------------------------------------------------------------
@@ -394,6 +419,7 @@ class Batch:
             check(self.lib.rflbm_batch_create(n, arr, None, 0, None, ctypes.byref(self._h)))
         self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         ptr = (_dev_ptr(self._buf) + 255) // 256 * 256
+        _after_torch(self.stream, self.device)
         check(self.lib.rflbm_batch_create(n, arr, _VP(ptr), nbytes, _VP(self.stream.cuda_stream),
                                           ctypes.byref(self._h)))
         self.views = []

@@ -388,3 +388,29 @@ def test_populations_at_outside_the_box_reads_nothing(rf, ora):
     with pytest.raises(ValueError):
         lat.populations_at([n])
     lat.close()
+
+
+def test_lattice_on_its_own_stream_matches_default_stream(rf, ora):
+    """A lattice created on a caller's stream (default priority) reaches bitwise
+    the state and moments of one on torch's current stream; inputs copied by
+    torch and results read by torch are ordered with the lattice stream."""
+    import torch
+
+    dims = (64, 6, 5)
+    kw = dict(kT=1e-4, tau=0.7, seed=21)
+    f = initial_state(ora, dims, seed=91)
+    rho, u = wl.random_velocity(dims, seed=92)
+    side = torch.cuda.Stream()
+    a, b = rf.Lattice(dims, **kw), rf.Lattice(dims, stream=side, **kw)
+    out = []
+    for lat in (a, b):
+        lat.init_equilibrium(rho, u)
+        lat.step(3)
+        lat.set_populations(f)
+        lat.step(7)
+        out.append((lat.populations().cpu(), lat.moments().cpu(), lat.populations_at([0, 5, 1919]).cpu()))
+        lat.sync()
+    for x, y in zip(*out):
+        assert torch.equal(x, y)
+    a.close()
+    b.close()
