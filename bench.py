@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -312,7 +313,6 @@ def summarize_valu(out_dir, storage, dims=(512, 512, 512)):
     the VALU instructions per node (SQ_INSTS_VALU counts wave instructions)."""
     import csv
     import glob
-    import re
 
     files = glob.glob(os.path.join(out_dir, f"prof_valu_{storage}", "*counter_collection.csv"))
     if not files:
@@ -375,9 +375,10 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
         # the odd step the whole-row kernel (the tiled ones when rows are off)
         if "copy_kernel" in name:
             return "copy"
-        if "step_row_kernel<0, 10>" in name or "step_kernel<0, true, 10, false>" in name:
+        # (the last template argument, every omega_g = 1, may follow)
+        if re.search(r"step_row_kernel<0, 10\b|step_kernel<0, true, 10, false\b", name):
             return "odd"
-        if "step_wave_kernel<0, 10>" in name or "step_kernel<0, false, 10, false>" in name:
+        if re.search(r"step_wave_kernel<0, 10\b|step_kernel<0, false, 10, false\b", name):
             return "even"
         return None
 

@@ -24,7 +24,8 @@
 // in one-wave x-segments), step_row_kernel (odd steps in whole x-rows, where
 // values move between lanes so that every access covers whole cache lines)
 // and batch_kernel (many boxes, persistent grid over tiles of consecutive
-// nodes).
+// nodes).  The three one-box kernels take GEQ (every omega_g = 1) as a template
+// parameter; the batch kernel reads it per replica.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -180,7 +181,7 @@ __device__ __forceinline__ void row_shift(uint32_t (&v)[kQ], uint32_t (*edge)[kM
 }
 
 // One box: a block covers bx x by nodes of one z plane (blockDim = (bx, by)).
-template <int S, bool ODD, int ROUNDS, bool STATS>
+template <int S, bool ODD, int ROUNDS, bool STATS, bool GEQ>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
   uint32_t tile = blockIdx.x;
   if (a.xcd_remap) tile = (tile & 7u) * (gridDim.x >> 3) + (tile >> 3);
@@ -200,6 +201,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     constexpr bool SMALL_BOX = false;
     constexpr bool BUFFER_ACCESS = true;
     constexpr bool ROW_SHIFT = false;
+    constexpr bool GHOST_EQ = GEQ;
     [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
     [[maybe_unused]] uint32_t (*row_edge_out)[kMaxRowWaves] = nullptr;
 #include "node_body.inc"
@@ -231,9 +233,10 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 
 // Even step without statistics in one-wave blocks: block b covers the 64
 // nodes x = 64 (b mod (nx / 64)) + lane of one x-row (nx a multiple of 64).
-template <int S, int ROUNDS>
+template <int S, int ROUNDS, bool GEQ>
 __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
   constexpr bool ODD = false, STATS = false, SMALL_BOX = false, ROW_SHIFT = false, BUFFER_ACCESS = true;
+  constexpr bool GHOST_EQ = GEQ;
   [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
   [[maybe_unused]] const uint32_t tid = 0;
   [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
@@ -254,9 +257,10 @@ __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
 // row index y + ny z (blockDim.x = nx, a multiple of 64 up to 1024), so that
 // the +-1 shifts in x stay inside the block and every load and store is a
 // whole aligned cache line (see row_shift).  Without statistics.
-template <int S, int ROUNDS>
+template <int S, int ROUNDS, bool GEQ>
 __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepArgs a) {
   constexpr bool ODD = true, STATS = false, SMALL_BOX = false, ROW_SHIFT = true, BUFFER_ACCESS = true;
+  constexpr bool GHOST_EQ = GEQ;
   [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
   [[maybe_unused]] const uint32_t tid = 0;
   __shared__ uint32_t row_edge_in[18][kMaxRowWaves];   // gather (stored words)
@@ -322,6 +326,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
       const uint32_t rem = n - z * (a.nx * a.ny);
       const uint32_t y = fast_div(rem, FastDiv{r.div_x.m, r.div_x.s});
       const uint32_t x = rem - y * a.nx;
+      const bool GHOST_EQ = a.ghost_eq != 0u;
 #include "node_body.inc"
     }
   }
@@ -371,8 +376,23 @@ __global__ void accumulate_stats(const double* sums, double* acc) {
 
 template <int S, bool ODD, int R, bool ST>
 hipError_t launch_t(const StepArgs& a, const Launch& l, hipStream_t s) {
-  hipLaunchKernelGGL((step_kernel<S, ODD, R, ST>), dim3(l.grid), dim3(l.bx, l.by), 0, s, a);
+  if (a.ghost_eq)
+    hipLaunchKernelGGL((step_kernel<S, ODD, R, ST, true>), dim3(l.grid), dim3(l.bx, l.by), 0, s, a);
+  else
+    hipLaunchKernelGGL((step_kernel<S, ODD, R, ST, false>), dim3(l.grid), dim3(l.bx, l.by), 0, s, a);
   return hipGetLastError();
+}
+
+template <int S, int R>
+void launch_row_g(const StepArgs& a, dim3 g, dim3 blk, hipStream_t s) {
+  if (a.ghost_eq) hipLaunchKernelGGL((step_row_kernel<S, R, true>), g, blk, 0, s, a);
+  else hipLaunchKernelGGL((step_row_kernel<S, R, false>), g, blk, 0, s, a);
+}
+
+template <int S, int R>
+void launch_wave_g(const StepArgs& a, dim3 g, hipStream_t s) {
+  if (a.ghost_eq) hipLaunchKernelGGL((step_wave_kernel<S, R, true>), g, dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((step_wave_kernel<S, R, false>), g, dim3(64), 0, s, a);
 }
 
 template <int S, bool ODD, bool ST>
@@ -396,9 +416,9 @@ template <int S>
 hipError_t launch_row_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_t s) {
   const dim3 g(grid), blk(a.nx);
   switch (rounds) {
-    case 0: hipLaunchKernelGGL((step_row_kernel<S, 0>), g, blk, 0, s, a); break;
-    case 7: hipLaunchKernelGGL((step_row_kernel<S, 7>), g, blk, 0, s, a); break;
-    case 10: hipLaunchKernelGGL((step_row_kernel<S, 10>), g, blk, 0, s, a); break;
+    case 0: launch_row_g<S, 0>(a, g, blk, s); break;
+    case 7: launch_row_g<S, 7>(a, g, blk, s); break;
+    case 10: launch_row_g<S, 10>(a, g, blk, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -407,9 +427,9 @@ hipError_t launch_row_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_
 template <int S>
 hipError_t launch_wave_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_t s) {
   switch (rounds) {
-    case 0: hipLaunchKernelGGL((step_wave_kernel<S, 0>), dim3(grid), dim3(64), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((step_wave_kernel<S, 7>), dim3(grid), dim3(64), 0, s, a); break;
-    case 10: hipLaunchKernelGGL((step_wave_kernel<S, 10>), dim3(grid), dim3(64), 0, s, a); break;
+    case 0: launch_wave_g<S, 0>(a, dim3(grid), s); break;
+    case 7: launch_wave_g<S, 7>(a, dim3(grid), s); break;
+    case 10: launch_wave_g<S, 10>(a, dim3(grid), s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
