@@ -227,15 +227,17 @@ rflbm_status rflbm_set_launch(rflbm_lattice* lat, int32_t bx, int32_t xcd_remap)
 rflbm_status rflbm_get_launch(const rflbm_lattice* lat, int32_t* bx, int32_t* xcd_remap);
 
 /* Row-aligned blocks for the steps without statistics (the streaming of
- * Eq. eq:streaming in its two AA phases).  When enabled and nx is a multiple
- * of 64: every odd step runs one block per x-row (if nx <= 1024), so that the
- * shifts by c_x = +-1 stay inside a block (values move between lanes) and
- * every load and store covers whole aligned cache lines; every even step runs
- * one 64-node x-segment per block.  Statistics steps, and all steps when
+ * Eq. eq:streaming in its two AA phases), used where the step is bound by
+ * bandwidth: FP32 storage, or k_BT = 0.  When enabled and nx is a multiple of
+ * 64, every even step runs one 64-node x-segment per block, and every odd step
+ * one block per x-row (if nx <= 1024).  The shifts by c_x = +-1 then stay
+ * inside a block (values move between lanes), and every load and store covers
+ * whole aligned cache lines.  The 16-bit steps with noise are bound by
+ * arithmetic and keep the tiled kernel.  Statistics steps, and all steps when
  * disabled, keep the tiled shape of rflbm_set_launch.  Results are bit for bit
- * the same either way.  Enabled by rflbm_create for FP32 storage, disabled
- * for FP16/BF16 (whose step is bound by arithmetic rather than bandwidth).
- * rflbm_get_row_blocks sets *active to 1 when odd steps run in whole rows. */
+ * the same either way.  Enabled by rflbm_create.  rflbm_get_row_blocks sets
+ * *active to 1 when the next odd step runs in whole rows (it depends on
+ * storage, k_BT and nx). */
 rflbm_status rflbm_set_row_blocks(rflbm_lattice* lat, int32_t enable);
 rflbm_status rflbm_get_row_blocks(const rflbm_lattice* lat, int32_t* active);
 

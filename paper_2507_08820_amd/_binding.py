@@ -356,7 +356,8 @@ class Lattice:
     @property
     def row_blocks(self) -> bool:
         """True when odd steps run in whole-row blocks (aligned full-line loads and
-        stores); even steps then run in one-wave x-segments."""
+        stores: FP32 storage, or k_BT = 0, with n_x a multiple of 64 up to 1024).
+        Even steps of such lattices run in one-wave x-segments."""
         active = ctypes.c_int32()
         check(self.lib.rflbm_get_row_blocks(self._h, ctypes.byref(active)))
         return bool(active.value)

@@ -190,11 +190,21 @@ void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStre
   L->stream = s;
   L->launch = make_launch(p.nx, p.ny, p.nz, p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64),
                           p.nx >= 256 ? 1 : (p.nx >= 128 ? 2 : 4));
-  // row-aligned blocks (whole-row odd steps, one-wave even steps) pay off where
-  // the step is bandwidth bound (FP32); the 16-bit steps are bound by
-  // arithmetic, where the lane moves of the odd step cost more than they save
-  L->row_odd = p.storage == RFLBM_F32;
+  L->row_mode = true;
 }
+
+// Row-aligned blocks pay off where the step is bandwidth bound: FP32 storage,
+// or no noise (16-bit at 512^3 without noise: 2.46 ms per step against 2.74 ms
+// tiled).  The 16-bit steps with noise are bound by arithmetic: there the lane
+// moves and barriers of the whole-row odd step cost more than the aligned
+// accesses save (3.8 against 3.2 ms), and one-wave even steps between tiled
+// odd ones measured no faster than tiled ones (3.28-3.30 against 3.26-3.27 ms
+// per step), so those steps keep the tiled kernel.
+static bool rows_pay(const rflbm_lattice* L) {
+  return L->row_mode && (L->p.storage == RFLBM_F32 || L->p.kT == 0.0);
+}
+
+static bool odd_in_rows(const rflbm_lattice* L) { return rows_pay(L) && row_kernel_fits(L->p.nx); }
 
 hipError_t lattice_clear(rflbm_lattice* L) {
   // populations (deviation 0 = rest at rho0), flag and accumulators
@@ -280,9 +290,9 @@ rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps) {
     const bool stats = L->stats_every > 0 && (t % L->stats_every) == 0;
     a.step = static_cast<uint32_t>(t & 0xffffffffu);
     const bool odd = (t & 1) != 0;
-    if (odd && !stats && L->row_odd && row_kernel_fits(L->p.nx))
+    if (odd && !stats && odd_in_rows(L))
       RFLBM_HIP(launch_step_row(L->p.storage, rounds, a, L->stream));
-    else if (!odd && !stats && L->row_odd && L->p.nx % 64 == 0)
+    else if (!odd && !stats && rows_pay(L) && L->p.nx % 64 == 0)
       RFLBM_HIP(launch_step_wave(L->p.storage, rounds, a, L->stream));
     else
       RFLBM_HIP(launch_step(L->p.storage, odd, rounds, stats, a, L->launch, L->stream));
@@ -645,14 +655,14 @@ rflbm_status rflbm_get_launch(const rflbm_lattice* L, int32_t* bx, int32_t* xcd_
 
 rflbm_status rflbm_set_row_blocks(rflbm_lattice* L, int32_t enable) {
   if (rflbm_status s = check_lattice(L)) return s;
-  L->row_odd = enable != 0;
+  L->row_mode = enable != 0;
   return RFLBM_OK;
 }
 
 rflbm_status rflbm_get_row_blocks(const rflbm_lattice* L, int32_t* active) {
   if (rflbm_status s = check_lattice(L)) return s;
   if (!active) return fail(RFLBM_EINVAL, "active is NULL");
-  *active = L->row_odd && row_kernel_fits(L->p.nx) ? 1 : 0;
+  *active = odd_in_rows(L) ? 1 : 0;
   return RFLBM_OK;
 }
 

@@ -61,9 +61,10 @@ struct rflbm_lattice {
   int32_t stats_every = 0;
   rflbm::Launch launch{};
   bool xcd_remap = true;
-  // row-aligned blocks for steps without statistics (FP32 default): odd steps
-  // in whole-row blocks when nx fits, even steps in one-wave x-segments
-  bool row_odd = true;
+  // row-aligned blocks for steps without statistics (on by default), used
+  // where the step is bandwidth bound (FP32 storage, or k_BT = 0): even steps
+  // in one-wave x-segments, odd steps in whole-row blocks when nx fits
+  bool row_mode = true;
   // S(k) state (library-allocated on first use)
   hipfftHandle plan = 0;
   bool have_plan = false;

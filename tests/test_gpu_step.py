@@ -106,18 +106,21 @@ def test_trajectory_matches_oracle(rf, ora, case):
     print(f"[gpu] {case}: worst relative error over {steps} steps {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("kT", [1e-4, 0.0])
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("dims", [(64, 3, 5), (128, 4, 3), (320, 2, 3), (1024, 3, 2)])
-def test_row_blocks_match_tiled_bitwise(rf, ora, dims, storage):
-    """The whole-row odd step and the tiled one store the same bits; mixed
-    with statistics steps (which take the tiled kernel) and both parities."""
-    print(f"[gpu] row blocks vs tiles {dims} {storage}", flush=True)
+def test_row_blocks_match_tiled_bitwise(rf, ora, dims, storage, kT):
+    """The row-aligned steps (one-wave even steps, whole-row odd steps; used for
+    FP32 and for k_BT = 0) store the same bits as the tiled ones; mixed with
+    statistics steps (which take the tiled kernel) and both parities."""
+    print(f"[gpu] row blocks vs tiles {dims} {storage} kT={kT}", flush=True)
     f = initial_state(ora, dims, seed=21)
+    extra = dict(storage_scale=1e-2) if (storage != "f32" and kT == 0.0) else {}
     lats = []
     for rows in (True, False):
-        lat = rf.Lattice(dims, storage=storage, kT=1e-4, tau=0.6, tau_bulk=0.8, seed=4)
+        lat = rf.Lattice(dims, storage=storage, kT=kT, tau=0.6, tau_bulk=0.8, seed=4, **extra)
         lat.set_row_blocks(rows)
-        assert lat.row_blocks == rows
+        assert lat.row_blocks == (rows and (storage == "f32" or kT == 0.0))
         lat.set_populations(f)
         lat.stats_config(4)
         lat.step(9)
