@@ -90,6 +90,7 @@ struct rflbm_batch {
   int32_t bpc = 8;         // persistent blocks per CU (0: one block per tile)
   int32_t graph_steps = 0; // steps per captured graph (0: no graph)
   uint32_t ntiles = 0;
+  bool all_ghost_eq = false;  // every replica has every omega_g = 1
   int cus = 0;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -116,10 +117,12 @@ rflbm_status upload_tables(rflbm_batch* b) {
   std::vector<ReplicaArgs> reps(b->n);
   std::vector<uint32_t> tile_rep;
   uint32_t t0 = 0;
+  bool all_geq = true;
   for (int32_t r = 0; r < b->n; ++r) {
     ReplicaArgs& ra = reps[r];
     std::memset(&ra, 0, sizeof(ra));
     ra.a = step_args(b->views[r]);
+    all_geq = all_geq && ra.a.ghost_eq != 0u;
     const rflbm_params& p = b->p[r];
     ra.nodes = static_cast<uint32_t>(node_count(p));
     ra.tile0 = t0;
@@ -130,6 +133,7 @@ rflbm_status upload_tables(rflbm_batch* b) {
     t0 += nt;
   }
   b->ntiles = t0;
+  b->all_ghost_eq = all_geq;
   RFLBM_HIP(hipMemcpyAsync(b->buf + b->B.reps_off, reps.data(), reps.size() * sizeof(ReplicaArgs),
                            hipMemcpyHostToDevice, b->stream));
   RFLBM_HIP(hipMemcpyAsync(b->buf + b->B.tiles_off, tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
@@ -157,7 +161,7 @@ uint32_t batch_grid(const rflbm_batch* b) {
 // Enqueues one step of parity (t & 1) plus the device counter update.
 hipError_t enqueue_step(rflbm_batch* b, bool odd, hipStream_t s) {
   const BatchArgs a = batch_args(b);
-  hipError_t e = launch_batch_step(b->p[0].storage, odd, b->rounds, a, batch_grid(b), b->tile, s);
+  hipError_t e = launch_batch_step(b->p[0].storage, odd, b->rounds, b->all_ghost_eq, a, batch_grid(b), b->tile, s);
   if (e != hipSuccess) return e;
   return launch_advance_step(reinterpret_cast<uint32_t*>(b->buf + b->B.step_off), s);
 }

@@ -77,9 +77,10 @@ struct BatchArgs {
 
 // One step of every replica (persistent grid of `grid` blocks walking the tiles);
 // the Philox step counter is read from b.step on the device, the parity `odd`
-// must match it.
-hipError_t launch_batch_step(int storage, bool odd, int rounds, const BatchArgs& b, uint32_t grid,
-                             uint32_t tile, hipStream_t stream);
+// must match it.  all_ghost_eq: every replica has every omega_g = 1 (then the
+// kernel variant without the general ghost relaxation runs).
+hipError_t launch_batch_step(int storage, bool odd, int rounds, bool all_ghost_eq, const BatchArgs& b,
+                             uint32_t grid, uint32_t tile, hipStream_t stream);
 // *step += 1 on the device (a graph node after each captured batch step).
 hipError_t launch_advance_step(uint32_t* step, hipStream_t stream);
 
@@ -124,8 +125,8 @@ struct GatherArgs {
 
 // f(x, t) -> dst[i * N + n] (FP64, absolute populations).
 hipError_t launch_get_populations(int storage, const GatherArgs& g, double* dst, hipStream_t s);
-// f(x, t) at nodes[0..count) -> dst[i * count + k] (FP64, absolute); the
-// node indices must be < nx ny nz.
+// f(x, t) at nodes[0..count) -> dst[i * count + k] (FP64, absolute); an index
+// >= nx ny nz reads nothing and yields NaN.
 hipError_t launch_get_populations_at(int storage, const GatherArgs& g, const uint32_t* nodes,
                                      uint32_t count, double* dst, hipStream_t s);
 // src[i * N + n] (FP64, absolute) -> storage slots for step parity g.odd.

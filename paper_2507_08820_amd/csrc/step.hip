@@ -25,7 +25,8 @@
 // values move between lanes so that every access covers whole cache lines)
 // and batch_kernel (many boxes, persistent grid over tiles of consecutive
 // nodes).  The three one-box kernels take GEQ (every omega_g = 1) as a template
-// parameter; the batch kernel reads it per replica.
+// parameter, and so does the batch kernel when every replica has it (else it
+// reads the setting per replica).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -297,8 +298,10 @@ __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepA
 // replica tile_rep[t]; a persistent grid walks the tiles.  The step count (the
 // Philox counter) comes from device memory so that a captured graph of several
 // steps can be replayed; the parity is a template parameter, and the host only
-// replays graphs of an even number of steps from an even step count.
-template <int S, bool ODD, int ROUNDS>
+// replays graphs of an even number of steps from an even step count.  GEQ:
+// every replica has every omega_g = 1; otherwise each replica's own setting
+// is read at run time.
+template <int S, bool ODD, int ROUNDS, bool GEQ>
 __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
   constexpr bool STATS = false;
   constexpr bool SMALL_BOX = true;  // every replica region is below 4 GiB
@@ -326,7 +329,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
       const uint32_t rem = n - z * (a.nx * a.ny);
       const uint32_t y = fast_div(rem, FastDiv{r.div_x.m, r.div_x.s});
       const uint32_t x = rem - y * a.nx;
-      const bool GHOST_EQ = a.ghost_eq != 0u;
+      const bool GHOST_EQ = GEQ || a.ghost_eq != 0u;
 #include "node_body.inc"
     }
   }
@@ -485,15 +488,20 @@ hipError_t launch_step(int storage, bool odd, int rounds, bool stats, const Step
   }
 }
 
-hipError_t launch_batch_step(int storage, bool odd, int rounds, const BatchArgs& b, uint32_t grid,
-                             uint32_t tile, hipStream_t stream) {
+hipError_t launch_batch_step(int storage, bool odd, int rounds, bool all_ghost_eq, const BatchArgs& b,
+                             uint32_t grid, uint32_t tile, hipStream_t stream) {
   if (tile != 128 && tile != 256) return hipErrorInvalidConfiguration;
   const dim3 g(grid), blk(tile);
+#define RFLBM_BATCH_G(S, O, R)                                                                 \
+  if (all_ghost_eq)                                                                            \
+    hipLaunchKernelGGL((batch_kernel<S, O, R, true>), g, blk, 0, stream, b);                   \
+  else                                                                                         \
+    hipLaunchKernelGGL((batch_kernel<S, O, R, false>), g, blk, 0, stream, b);
 #define RFLBM_BATCH_R(S, O)                                                                    \
   switch (rounds) {                                                                            \
-    case 0: hipLaunchKernelGGL((batch_kernel<S, O, 0>), g, blk, 0, stream, b); break;          \
-    case 7: hipLaunchKernelGGL((batch_kernel<S, O, 7>), g, blk, 0, stream, b); break;          \
-    case 10: hipLaunchKernelGGL((batch_kernel<S, O, 10>), g, blk, 0, stream, b); break;        \
+    case 0: RFLBM_BATCH_G(S, O, 0) break;                                                      \
+    case 7: RFLBM_BATCH_G(S, O, 7) break;                                                      \
+    case 10: RFLBM_BATCH_G(S, O, 10) break;                                                    \
     default: return hipErrorInvalidValue;                                                      \
   }
 #define RFLBM_BATCH(S)            \
@@ -510,6 +518,7 @@ hipError_t launch_batch_step(int storage, bool odd, int rounds, const BatchArgs&
   }
 #undef RFLBM_BATCH
 #undef RFLBM_BATCH_R
+#undef RFLBM_BATCH_G
   return hipGetLastError();
 }
 
