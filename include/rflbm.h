@@ -150,7 +150,10 @@ rflbm_status rflbm_sync(rflbm_lattice* lat);
 /* Steps taken so far (the time t of the current state). */
 int64_t rflbm_step_count(const rflbm_lattice* lat);
 /* Sets t (checkpoint restart: set_populations + set_step_count resumes a run
- * bit for bit, since the noise depends only on (seed, n, t, stream_id)). */
+ * bit for bit, since the noise depends only on (seed, n, t, stream_id)).  A
+ * change of parity moves the stored state to the other AA layout in place and
+ * bit for bit, with a temporary device buffer of one population plane
+ * (nx ny nz stored words), freed before the call returns. */
 rflbm_status rflbm_set_step_count(rflbm_lattice* lat, int64_t t);
 
 /* Reads the populations f(x, t) (FP64, planar, 27 N values) into dst.  With a

@@ -20,6 +20,9 @@
 namespace rflbm {
 hipError_t launch_sk_bin(const void* spec, uint32_t nx, uint32_t ny, uint32_t nz, uint32_t nshells,
                          double* shell_sum, unsigned long long* shell_count, hipStream_t s);
+// Moves the stored state to the other AA parity in place, as raw stored words;
+// tmp holds one population plane (nx ny nz words of the storage type).
+hipError_t launch_swap_parity(int storage, const GatherArgs& g, void* tmp, hipStream_t s);
 }
 
 using namespace rflbm;
@@ -305,12 +308,12 @@ rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps) {
 rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t) {
   if (t < 0) return fail(RFLBM_EINVAL, "step count must be >= 0");
   if ((t & 1) != (L->t & 1)) {
-    // the storage layout depends on the parity: move the state to the new one
+    // the storage layout depends on the parity: move the state to the new one,
+    // in place and bit for bit, through one population plane of scratch
     const uint64_t N = nodes(L);
-    double* tmp = nullptr;
-    RFLBM_HIP(hipMalloc(&tmp, 27 * N * sizeof(double)));
-    hipError_t e = launch_get_populations(L->p.storage, gather_args(L, L->p, L->t), tmp, L->stream);
-    if (e == hipSuccess) e = launch_set_populations(L->p.storage, gather_args(L, L->p, t), tmp, L->stream);
+    void* tmp = nullptr;
+    RFLBM_HIP(hipMalloc(&tmp, N * storage_bytes(L->p.storage)));
+    hipError_t e = launch_swap_parity(L->p.storage, gather_args(L, L->p, L->t), tmp, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     (void)hipFree(tmp);
     if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("re-layout: ") + hipGetErrorString(e));

@@ -286,9 +286,69 @@ __global__ void set_u32_kernel(uint32_t* dst, uint32_t value) {
   if (threadIdx.x == 0) *dst = value;
 }
 
+// Parity change of the stored state: the slot of f_j(y) at the new parity is
+// A'[j][y] = A[26 - j][y - c_j] of the old one, in either direction.  The three
+// kernels below move raw stored words (W = the storage word) so that the state
+// is carried over bit for bit.
+// tmp[n] = A[plane][n] (tmp compact, node order).
+template <typename W>
+__global__ void plane_save_kernel(const GatherArgs g, int plane, W* tmp) {
+  const W* pop = static_cast<const W*>(g.pop);
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+    tmp[n] = pop[element_index(plane, p.x, p.y, p.z, g)];
+  }
+}
+
+// A[dst][y] = A[src][y - c] (dst != src), periodic.
+template <typename W>
+__global__ void plane_shift_kernel(const GatherArgs g, int dst, int src, int cx, int cy, int cz) {
+  W* pop = static_cast<W*>(const_cast<void*>(g.pop));
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+    pop[element_index(dst, p.x, p.y, p.z, g)] =
+        pop[element_index(src, wrap_add(p.x, -cx, g.nx), wrap_add(p.y, -cy, g.ny), wrap_add(p.z, -cz, g.nz), g)];
+  }
+}
+
+// A[dst][y] = tmp[y - c], periodic.
+template <typename W>
+__global__ void plane_restore_kernel(const GatherArgs g, int dst, const W* tmp, int cx, int cy, int cz) {
+  W* pop = static_cast<W*>(const_cast<void*>(g.pop));
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n, g.nx, g.ny);
+    const uint64_t q = wrap_add(p.x, -cx, g.nx) +
+                       static_cast<uint64_t>(g.nx) * (wrap_add(p.y, -cy, g.ny) +
+                                                      static_cast<uint64_t>(g.ny) * wrap_add(p.z, -cz, g.nz));
+    pop[element_index(dst, p.x, p.y, p.z, g)] = tmp[q];
+  }
+}
+
+
 uint32_t grid_for(uint64_t work, uint32_t block) {
   const uint64_t g = (work + block - 1) / block;
   return static_cast<uint32_t>(g < 65536 ? (g == 0 ? 1 : g) : 65536);
+}
+
+template <typename W>
+hipError_t swap_parity_words(const GatherArgs& g, W* tmp, hipStream_t s) {
+  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
+  const dim3 grid(grid_for(N, 256)), block(256);
+  // pairs (j, 26 - j), j < 13; the rest population (j = 13, c = 0) stays
+  for (int j = 0; j < kQ / 2; ++j) {
+    const int cx = j % 3 - 1, cy = (j / 3) % 3 - 1, cz = j / 9 - 1;
+    hipLaunchKernelGGL(plane_save_kernel<W>, grid, block, 0, s, g, j, tmp);
+    hipLaunchKernelGGL(plane_shift_kernel<W>, grid, block, 0, s, g, j, kQ - 1 - j, cx, cy, cz);
+    hipLaunchKernelGGL(plane_restore_kernel<W>, grid, block, 0, s, g, kQ - 1 - j, tmp, -cx, -cy, -cz);
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -377,6 +437,15 @@ hipError_t launch_rng_normals(uint32_t key0, uint32_t key1, uint32_t stream_id, 
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t launch_swap_parity(int storage, const GatherArgs& g, void* tmp, hipStream_t s) {
+  switch (storage) {
+    case kF32: return swap_parity_words(g, static_cast<uint32_t*>(tmp), s);
+    case kF16:
+    case kBF16: return swap_parity_words(g, static_cast<uint16_t*>(tmp), s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
