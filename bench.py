@@ -93,7 +93,11 @@ def run_gpu(dims, storage, kT, steps, warmup, tau=0.6, stats_every=0, followups=
     log(f"{dims} {storage} kT={kT}{f' stats every {stats_every}' if stats_every else ''}: {steps} steps, "
         f"{r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS")
     for label, f_kT, f_stats, f_steps in followups:
-        lat.set_params(**dict(kw, kT=f_kT))
+        f_kw = dict(kw, kT=f_kT)
+        if storage != "f32" and f_kT == 0.0:
+            # keep the storage unit the noisy run derived from k_BT, sqrt(rho0 kT / cs2)
+            f_kw["storage_scale"] = (3.0 * kT) ** 0.5
+        lat.set_params(**f_kw)
         lat.stats_config(f_stats)
         lat.step(2)
         f_ms = lat.time_steps(f_steps)
@@ -561,9 +565,12 @@ def main():
     extra = {}
     if not args.no_extra:
         for name, storage in (("f16_store", "f16"), ("bf16_store", "bf16")):
-            r = run_gpu(dims, storage, 1e-5, short, 5)
+            r = run_gpu(dims, storage, 1e-5, short, 5, followups=(("kT0_reg_lbm", 0.0, 0, short),))
             extra[name] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                            "hbm_gbs": round(BYTES_PER_UPDATE[storage] * n / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
+            # the deterministic step on the same lattice (bandwidth bound: row-aligned kernels)
+            f = r["followups"]["kT0_reg_lbm"]
+            extra[name + "_kT0"] = {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["ms_per_step"], 4)}
         # same lattice as the main figure
         for name, label in (("f32_stats_every_step", "stats_every_step"), ("reg_lbm_kT0_f32", "kT0_reg_lbm")):
             f = main_run["followups"][label]
