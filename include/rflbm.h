@@ -79,7 +79,7 @@ typedef struct {
   int32_t nx, ny, nz;      /* periodic box, each >= 2 (fixed at creation) */
   int32_t storage;         /* rflbm_storage (fixed at creation) */
   int32_t model;           /* rflbm_model */
-  uint32_t philox_rounds;  /* Philox rounds, 7..10; 10 is the default */
+  uint32_t philox_rounds;  /* Philox rounds, 7 or 10 (else EINVAL); 10 is the default */
   double rho0;             /* reference density > 0 (Sec. III: rho normalised to 1) */
   double kT;               /* k_B T >= 0; 0 gives the deterministic Reg-LBM (Sec. IV) */
   double tau_shear;        /* 1/omega_h on the deviatoric modes k = 4..9, > 1/2; the
