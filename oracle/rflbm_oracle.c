@@ -48,10 +48,12 @@
  *     z_2p+1 = R sin(theta), R = sqrt(-2 ln U_2p), theta = 2 pi U_2p+1; mode k
  *     (4..26) receives r_k = z_(k-4); z_23 is unused.
  *
- * Pins.  The Philox bit stream is "parity unpinned": no published known-answer
- * vectors are available here, so it is checked only statistically and for
- * CPU/GPU bit identity.  Every other function is pinned by the tests against
- * values printed in the paper and closed forms.
+ * Pins.  The Philox bit stream is pinned to the published definition of the
+ * round by inversion: the tests undo R rounds of that definition (its odd
+ * multipliers are invertible mod 2^32) and must recover every counter.  The
+ * uniforms and normals are pinned statistically and by their documented
+ * layout.  Every other function is pinned by the tests against values printed
+ * in the paper and closed forms.
  *
  * Layout of a lattice in this file: f[i * N + n], i the canonical population
  * index (c = (i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1)), n = x + nx (y + ny z).

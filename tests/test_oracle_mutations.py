@@ -4,7 +4,8 @@ Each case plants one mistake in a copy of the oracle's C source (on the CPU,
 in a scratch directory; the GPU path is not involved), rebuilds that copy and
 runs the oracle's pin tests against it: at least one pin must fail.  The
 mistakes are the kind a transcription of Table II, Eq. normal_fact,
-Eq. fluct_phi, Eq. r-flbe2 or Eq. eq:streaming could contain.  The unmutated
+Eq. fluct_phi, Eq. r-flbe2, Eq. eq:streaming or of the Philox round could
+contain.  The unmutated
 copy must pass, so a failure is the mistake's doing and not the harness's.
 """
 import os
@@ -15,7 +16,8 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PIN_TESTS = ["tests/test_oracle_tables.py", "tests/test_oracle_collide.py", "tests/test_oracle_dynamics.py"]
+PIN_TESTS = ["tests/test_oracle_tables.py", "tests/test_oracle_collide.py", "tests/test_oracle_dynamics.py",
+             "tests/test_philox.py"]
 
 # (name, text in rflbm_oracle.c, replacement)
 MUTATIONS = [
@@ -33,6 +35,9 @@ MUTATIONS = [
      "(fdt_factor(om_s) * r_mean + fdt_factor(om_b) * (r[k - 4] - r_mean))"),
     ("reference_density_in_phi", "const double mu = rho * p->kT / CS2;", "const double mu = p->rho0 * p->kT / CS2;"),
     ("streaming_direction", "const int32_t xd = (x + C[i][0] + nx) % nx;", "const int32_t xd = (x - C[i][0] + nx) % nx;"),
+    ("philox_key_increment", "#define PHILOX_WEYL_A 0x9E3779B9u", "#define PHILOX_WEYL_A 0x9E3779BBu"),
+    ("philox_product_word", "uint32_t n1 = (uint32_t)pb;", "uint32_t n1 = (uint32_t)pa;"),
+    ("philox_key_schedule", "    if (r > 0) {\n      k0 += PHILOX_WEYL_A;", "    if (r > 1) {\n      k0 += PHILOX_WEYL_A;"),
 ]
 
 

@@ -1,12 +1,13 @@
 """Checks of the oracle's counter-based normal generator.
 
 The paper does not name its random number generator.  This build uses
-Philox4x32-R (Salmon et al., SC'11) with Box-Muller; no published known-answer
-vectors are available in this environment, so the bit stream itself is parity
-unpinned.  What is checked here: the uniforms lie on the 24-bit grid and are
-uniform, the normals have the moments and distribution of N(0, 1), the Box-Muller
-pairing follows the documented counter layout, and draws at neighbouring
-counters (node, step, call) are uncorrelated.
+Philox4x32-R (Salmon et al., SC'11) with Box-Muller.  The bit stream is pinned
+to the published definition of the round without any known-answer vectors:
+undoing R rounds of that definition (its multipliers are odd, hence invertible
+mod 2^32) must give back the counter of every draw.  Also checked: the uniforms
+lie on the 24-bit grid and are uniform, the normals have the moments and
+distribution of N(0, 1), the Box-Muller pairing follows the documented counter
+layout, and draws at neighbouring counters (node, step, call) are uncorrelated.
 """
 import numpy as np
 import pytest
@@ -82,3 +83,39 @@ def test_key_rounds_and_determinism(ora):
 def test_seven_round_variant_is_also_normal(ora):
     z = draw(ora, range(10000), rounds=7)[:, :23].ravel()
     assert stats.kstest(z, "norm").pvalue > 1e-4
+
+
+# The Philox4x32 round as Salmon, Moraes, Dror and Shaw define it (SC'11):
+# the multipliers of counter words 0 and 2, and the Weyl increments by which
+# the two key words advance from one round to the next.
+PHILOX_M0, PHILOX_M2 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+MASK32 = 0xFFFFFFFF
+
+
+def undo_round(y, k0, k1):
+    """Inverse of one round with key (k0, k1).  The multipliers are odd, so the
+    low product words give back counter words 0 and 2; with them the high
+    product words, which were mixed into words 1 and 3, are known again."""
+    y0, y1, y2, y3 = y
+    x2 = (y1 * pow(PHILOX_M2, -1, 1 << 32)) & MASK32
+    x0 = (y3 * pow(PHILOX_M0, -1, 1 << 32)) & MASK32
+    x1 = y0 ^ ((PHILOX_M2 * x2) >> 32) ^ k0
+    x3 = y2 ^ ((PHILOX_M0 * x0) >> 32) ^ k1
+    return [x0, x1, x2, x3]
+
+
+@pytest.mark.parametrize("rounds", [7, 10])
+def test_philox_is_the_published_round_bit_for_bit(ora, rounds):
+    """Undoing `rounds` rounds of the published definition, with the key of
+    round r advanced r times by the published increments, gives back the
+    counter of every draw.  So the oracle's generator is that definition bit
+    for bit: word order, multipliers, key schedule and round count are pinned."""
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        ctr = [int(v) for v in rng.integers(0, 1 << 32, 4, dtype=np.uint64)]
+        key = [int(v) for v in rng.integers(0, 1 << 32, 2, dtype=np.uint64)]
+        y = [int(v) for v in ora.philox4x32(ctr, key, rounds)]
+        for r in reversed(range(rounds)):
+            y = undo_round(y, (key[0] + r * PHILOX_W0) & MASK32, (key[1] + r * PHILOX_W1) & MASK32)
+        assert y == ctr
