@@ -354,6 +354,43 @@ PROFILE_CMDS = {
 }
 
 
+TRACE16_CMD = ("rocprofv3 --kernel-trace --stats -d <out>/prof_trace_{s} -o trace --output-format csv "
+               "-- python3 bench.py --profile --profile-storage {s} --profile-steps 40")
+
+
+def summarize_trace(out_dir, storage, dims=(512, 512, 512)):
+    """profiles/step_<storage>_512_kernel_trace.txt for a 16-bit storage: the
+    rocprofv3 kernel statistics of a profiling run of 10 warm-up + 40 timed
+    steps and the mean of the even and odd step kernels (warm-up included)."""
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(out_dir, f"prof_trace_{storage}", "*kernel_stats.csv"))
+    if not files:
+        raise FileNotFoundError(f"prof_trace_{storage}")
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    n = dims[0] * dims[1] * dims[2]
+    steps = [r for r in rows if re.search(r"step_\w*kernel<", r["Name"])]
+    path = os.path.join(ROOT, "profiles", f"step_{storage}_512_kernel_trace.txt")
+    with open(path, "w") as fh:
+        fh.write(f"# rocprofv3 kernel statistics, 512^3 {storage.upper()} bench workload (k_BT = 1e-5,\n")
+        fh.write("# 10 warm-up + 40 timed steps, averages include the warm-up; one launch per step)\n")
+        fh.write(f"# command: {TRACE16_CMD.format(s=storage)}\n")
+        fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
+        fh.write("Name | Calls | AverageNs | MinNs | MaxNs\n")
+        for r in steps:
+            fh.write(f"{r['Name']} | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['MinNs']} | {r['MaxNs']}\n")
+        total = sum(float(r["AverageNs"]) * int(r["Calls"]) for r in steps)
+        calls = sum(int(r["Calls"]) for r in steps)
+        if calls:
+            mean = total / calls
+            fh.write(f"# mean step kernel: {mean:.0f} ns -> "
+                     f"{BYTES_PER_UPDATE[storage] * n / (mean * 1e-9) / 1e9:.1f} GB/s algorithmic, "
+                     f"{n / (mean * 1e-9) / 1e6:.0f} MLUPS\n")
+    return path
+
+
 def summarize_profiles(out_dir, dims=(512, 512, 512)):
     """Writes the profiles/ summaries from the CSVs of the three rocprofv3 runs
     of `bench.py --profile` (kernel trace, FETCH_SIZE, WRITE_SIZE)."""
@@ -434,12 +471,12 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
     return traffic, dur
 
 
-def profile_run(dims, storage="f32"):
+def profile_run(dims, storage="f32", steps=4):
     import torch
 
     import paper_2507_08820_amd as rf
 
-    run_gpu(dims, storage, 1e-5, 4, 2)
+    run_gpu(dims, storage, 1e-5, steps, 2 if steps <= 4 else 10)
     nbytes = 1 << 30
     src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -513,8 +550,12 @@ def main():
                     help="with --table3: measured steps (400 statistics samples, 40 S(k) snapshots)")
     ap.add_argument("--profile-storage", default="f32", choices=["f32", "f16", "bf16"],
                     help="with --profile: storage of the profiled workload")
+    ap.add_argument("--profile-steps", type=int, default=4,
+                    help="with --profile: timed steps (2 warm-up steps up to 4, else 10)")
     ap.add_argument("--summarize-valu", metavar="DIR",
                     help="write profiles/step_<storage>_512_valu.txt from the VALU counter CSVs under DIR")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="write profiles/step_{f16,bf16}_512_kernel_trace.txt from the kernel-trace CSVs under DIR")
     ap.add_argument("--precision512", action="store_true",
                     help="storage precision on the 512^3 workload: FP16 and BF16 against FP32 with "
                          "the same noise, kT in {1e-4, 1e-5, 1e-6}, 1000 steps")
@@ -534,11 +575,15 @@ def main():
         print(summarize_profiles(args.summarize))
         return
     if args.profile:
-        profile_run(dims, args.profile_storage)
+        profile_run(dims, args.profile_storage, args.profile_steps)
         return
     if args.summarize_valu:
         for storage in ("f32", "f16"):
             print(summarize_valu(args.summarize_valu, storage))
+        return
+    if args.summarize_trace:
+        for storage in ("f16", "bf16"):
+            print(summarize_trace(args.summarize_trace, storage))
         return
     if args.precision512:
         print(json.dumps(precision_full()))

@@ -89,3 +89,20 @@ def test_valu_summary(tmp_path, fake_root):
     assert "step_row_kernel<0, 10, true> | 3 | 75.0 | 833" in text
     assert "step_kernel<0, false, 10, true, true> | 3 | 100.0 | 763" in text
     assert "copy_kernel" not in text
+
+
+def test_16bit_trace_summary(tmp_path, fake_root):
+    dims = (8, 8, 8)
+    out = tmp_path / "out"
+    even = "void rflbm::(anonymous namespace)::step_kernel<1, false, 10, false, true>(rflbm::StepArgs)"
+    odd = "void rflbm::(anonymous namespace)::step_kernel<1, true, 10, false, true>(rflbm::StepArgs)"
+    stats = [dict(Name=even, Calls=3, AverageNs=3000.0, MinNs=2990, MaxNs=3010),
+             dict(Name=odd, Calls=3, AverageNs=3400.0, MinNs=3390, MaxNs=3410),
+             dict(Name=COPY, Calls=1, AverageNs=100.0, MinNs=100, MaxNs=100)]
+    write_csv(str(out / "prof_trace_f16" / "trace_kernel_stats.csv"), ["Name", "Calls", "AverageNs", "MinNs", "MaxNs"], stats)
+    path = bench.summarize_trace(str(out), "f16", dims=dims)
+    text = open(path).read()
+    assert even in text and odd in text and "copy_kernel" not in text
+    n = 8 * 8 * 8
+    assert f"mean step kernel: 3200 ns -> {108 * n / 3200e-9 / 1e9:.1f} GB/s" in text
+    assert f"{n / 3200e-9 / 1e6:.0f} MLUPS" in text
