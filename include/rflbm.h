@@ -153,7 +153,9 @@ int64_t rflbm_step_count(const rflbm_lattice* lat);
  * bit for bit, since the noise depends only on (seed, n, t, stream_id)).  A
  * change of parity moves the stored state to the other AA layout in place and
  * bit for bit, with a temporary device buffer of one population plane
- * (nx ny nz stored words), freed before the call returns. */
+ * (nx ny nz stored words), freed before the call returns.  ENOMEM (no room for
+ * that buffer) leaves the lattice unchanged; after an EHIP during the move the
+ * stored populations are undefined until they are set again. */
 rflbm_status rflbm_set_step_count(rflbm_lattice* lat, int64_t t);
 
 /* Reads the populations f(x, t) (FP64, planar, 27 N values) into dst.  With a

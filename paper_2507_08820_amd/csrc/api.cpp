@@ -312,11 +312,12 @@ rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t) {
     // in place and bit for bit, through one population plane of scratch
     const uint64_t N = nodes(L);
     void* tmp = nullptr;
-    RFLBM_HIP(hipMalloc(&tmp, N * storage_bytes(L->p.storage)));
+    if (const hipError_t m = hipMalloc(&tmp, N * storage_bytes(L->p.storage)); m != hipSuccess)
+      return hip_fail(RFLBM_ENOMEM, "re-layout scratch", m);
     hipError_t e = launch_swap_parity(L->p.storage, gather_args(L, L->p, L->t), tmp, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     (void)hipFree(tmp);
-    if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("re-layout: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return hip_fail(RFLBM_EHIP, "re-layout", e);
   }
   L->t = t;
   return RFLBM_OK;
@@ -369,7 +370,7 @@ rflbm_status rflbm_create(const rflbm_params* p, void* dev_buf, size_t bytes, vo
     const hipError_t e = hipMalloc(&b, lay.total);
     if (e != hipSuccess) {
       delete L;
-      return fail(RFLBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      return hip_fail(RFLBM_ENOMEM, "hipMalloc", e);
     }
     buf = static_cast<uint8_t*>(b);
     L->owns_buf = true;
@@ -379,7 +380,7 @@ rflbm_status rflbm_create(const rflbm_params* p, void* dev_buf, size_t bytes, vo
   if (e != hipSuccess) {
     lattice_release(L);
     delete L;
-    return fail(RFLBM_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    return hip_fail(RFLBM_EHIP, "hipMemsetAsync", e);
   }
   *out = L;
   return RFLBM_OK;
@@ -480,7 +481,7 @@ rflbm_status rflbm_get_populations(rflbm_lattice* L, double* dst, int dst_is_hos
   if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, 27 * N * sizeof(double), hipMemcpyDeviceToHost, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("get_populations: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail(RFLBM_EHIP, "get_populations", e);
   return RFLBM_OK;
 }
 
@@ -521,7 +522,7 @@ rflbm_status rflbm_get_moments(rflbm_lattice* L, uint32_t mask, float* dst, int 
   if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, nf * N * sizeof(float), hipMemcpyDeviceToHost, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("get_moments: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail(RFLBM_EHIP, "get_moments", e);
   return RFLBM_OK;
 }
 
@@ -687,7 +688,7 @@ rflbm_status rflbm_time_steps(rflbm_lattice* L, int64_t nsteps, double* ms) {
   if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("timing: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail(RFLBM_EHIP, "timing", e);
   if (st != RFLBM_OK) return st;
   *ms = f;
   return RFLBM_OK;

@@ -181,7 +181,7 @@ rflbm_status build_graph(rflbm_batch* b) {
   if (e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
     b->exec = nullptr;
-    return fail(RFLBM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    return hip_fail(RFLBM_EHIP, "graph capture", e);
   }
   b->graph = g;
   b->exec_steps = b->graph_steps;
@@ -226,7 +226,7 @@ rflbm_status time_batch(rflbm_batch* b, int64_t nsteps, double* ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != RFLBM_OK) return st;
-  if (e != hipSuccess) return fail(RFLBM_EHIP, std::string("timing: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail(RFLBM_EHIP, "timing", e);
   *ms = f;
   return RFLBM_OK;
 }
@@ -284,7 +284,7 @@ rflbm_status rflbm_batch_create(int32_t n, const rflbm_params* p, void* dev_buf,
     const hipError_t e = hipMalloc(&m, B.total);
     if (e != hipSuccess) {
       delete b;
-      return fail(RFLBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      return hip_fail(RFLBM_ENOMEM, "hipMalloc", e);
     }
     b->buf = static_cast<uint8_t*>(m);
     b->owns_buf = true;

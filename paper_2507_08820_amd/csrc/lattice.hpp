@@ -94,9 +94,18 @@ rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t);
 
 }  // namespace rflbm
 
-#define RFLBM_HIP(call)                                                                     \
-  do {                                                                                      \
-    const hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess)                                                                   \
-      return ::rflbm::fail(RFLBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+namespace rflbm {
+// Reports a failed HIP call.  HIP keeps the error as the thread's last error,
+// which the launch wrappers read back after every launch; it is cleared here
+// so that a later, unrelated call does not report it again.
+inline rflbm_status hip_fail(rflbm_status st, const std::string& what, hipError_t e) {
+  (void)hipGetLastError();
+  return fail(st, what + ": " + hipGetErrorString(e));
+}
+}  // namespace rflbm
+
+#define RFLBM_HIP(call)                                                  \
+  do {                                                                   \
+    const hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) return ::rflbm::hip_fail(RFLBM_EHIP, #call, e_); \
   } while (0)

@@ -437,3 +437,32 @@ def test_parity_change_keeps_the_state_bitwise(rf, ora, storage):
     assert torch.equal(f0, f1) and torch.equal(f0, f2)
     lat.sync()
     lat.close()
+
+
+def test_failed_allocation_is_not_reported_again_later(rf):
+    """A lattice too large for the device fails with ENOMEM; the calls that
+    follow (a small lattice created, initialised, stepped and synchronised,
+    all through the C interface) succeed: the failed allocation is not
+    reported again by the next kernel launch."""
+    import ctypes
+
+    from paper_2507_08820_amd import _binding
+
+    lib = rf.load_library()
+    big = _binding.make_params((1600, 1600, 1600))  # about 442 GB in FP32, more than the device holds
+    assert lib.rflbm_required_bytes(ctypes.byref(big)) > 400e9
+    h = _binding._VP()
+    rc = lib.rflbm_create(ctypes.byref(big), None, 0, None, ctypes.byref(h))
+    if rc == _binding.OK:
+        lib.rflbm_destroy(h)
+    assert rc == _binding.ENOMEM
+    small = _binding.make_params((64, 4, 4), kT=1e-4, tau=0.8)
+    h = _binding._VP()
+    assert lib.rflbm_create(ctypes.byref(small), None, 0, None, ctypes.byref(h)) == _binding.OK
+    try:
+        assert lib.rflbm_init_equilibrium(h, None, None, 0) == _binding.OK
+        assert lib.rflbm_step(h, 3) == _binding.OK
+        assert lib.rflbm_sync(h) == _binding.OK
+        assert lib.rflbm_step_count(h) == 3
+    finally:
+        lib.rflbm_destroy(h)
