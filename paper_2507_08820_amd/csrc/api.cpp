@@ -676,7 +676,10 @@ rflbm_status rflbm_time_steps(rflbm_lattice* L, int64_t nsteps, double* ms) {
   if (!ms) return fail(RFLBM_EINVAL, "ms is NULL");
   hipEvent_t e0, e1;
   RFLBM_HIP(hipEventCreate(&e0));
-  RFLBM_HIP(hipEventCreate(&e1));
+  if (const hipError_t c = hipEventCreate(&e1); c != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(RFLBM_EHIP, "hipEventCreate", c);
+  }
   rflbm_status st = RFLBM_OK;
   hipError_t e = hipEventRecord(e0, L->stream);
   if (e == hipSuccess) {

@@ -193,27 +193,38 @@ rflbm_status do_batch_steps(rflbm_batch* b, int64_t nsteps) {
   for (rflbm_lattice* v : b->views)
     if (v->t != b->t) return fail(RFLBM_ESTATE, "a replica was stepped or re-timed on its own");
   int64_t left = nsteps;
-  while (left > 0) {
+  rflbm_status st = RFLBM_OK;
+  while (left > 0 && st == RFLBM_OK) {
     if (b->graph_steps > 0 && (b->t & 1) == 0 && left >= b->graph_steps) {
-      if (b->exec_steps != b->graph_steps)
-        if (rflbm_status s = build_graph(b)) return s;
-      RFLBM_HIP(hipGraphLaunch(b->exec, b->stream));
+      if (b->exec_steps != b->graph_steps) st = build_graph(b);
+      if (st != RFLBM_OK) break;
+      if (const hipError_t e = hipGraphLaunch(b->exec, b->stream); e != hipSuccess) {
+        st = hip_fail(RFLBM_EHIP, "hipGraphLaunch", e);
+        break;
+      }
       b->t += b->graph_steps;
       left -= b->graph_steps;
     } else {
-      RFLBM_HIP(enqueue_step(b, (b->t & 1) != 0, b->stream));
+      if (const hipError_t e = enqueue_step(b, (b->t & 1) != 0, b->stream); e != hipSuccess) {
+        st = hip_fail(RFLBM_EHIP, "batch step", e);
+        break;
+      }
       b->t += 1;
       left -= 1;
     }
   }
+  // the replicas share the batch's step count, also after a failed launch
   for (rflbm_lattice* v : b->views) v->t = b->t;
-  return RFLBM_OK;
+  return st;
 }
 
 rflbm_status time_batch(rflbm_batch* b, int64_t nsteps, double* ms) {
   hipEvent_t e0, e1;
   RFLBM_HIP(hipEventCreate(&e0));
-  RFLBM_HIP(hipEventCreate(&e1));
+  if (const hipError_t c = hipEventCreate(&e1); c != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(RFLBM_EHIP, "hipEventCreate", c);
+  }
   hipError_t e = hipEventRecord(e0, b->stream);
   rflbm_status st = RFLBM_OK;
   if (e == hipSuccess) {
