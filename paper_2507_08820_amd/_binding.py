@@ -168,6 +168,26 @@ def make_params(dims, *, storage="f32", model="reg", kT=0.0, tau=1.0, tau_bulk=N
     return p
 
 
+def params_kwargs(p: Params) -> dict:
+    """The make_params keywords that reproduce p (the box aside)."""
+    storage = {v: k for k, v in STORAGE.items()}[p.storage]
+    model = {v: k for k, v in MODEL.items()}[p.model]
+    return dict(storage=storage, model=model, kT=p.kT, tau=p.tau_shear, tau_bulk=p.tau_bulk,
+                tau_ghost=[p.tau_ghost[k] for k in range(17)], rho0=p.rho0, seed=p.seed,
+                stream_id=p.stream_id, philox_rounds=p.philox_rounds, storage_scale=p.storage_scale)
+
+
+def merged_params(current: Params, dims, **changes) -> Params:
+    """current with the given make_params keywords changed; every other field
+    keeps its value.  A new tau without tau_bulk also sets the bulk rate when
+    that rate followed the shear rate before (tau_bulk == tau)."""
+    kw = params_kwargs(current)
+    if "tau" in changes and "tau_bulk" not in changes and current.tau_bulk == current.tau_shear:
+        kw["tau_bulk"] = None
+    kw.update(changes)
+    return make_params(dims, **kw)
+
+
 def _torch():
     import torch
     return torch
@@ -268,7 +288,9 @@ class Lattice:
         check(self.lib.rflbm_set_step_count(self._h, int(value)))
 
     def set_params(self, **kw):
-        p = make_params(self.dims, **kw)
+        """Changes the given make_params keywords; the others keep their values
+        (see merged_params).  Box and storage type are fixed at creation."""
+        p = merged_params(self.params, self.dims, **kw)
         check(self.lib.rflbm_set_params(self._h, ctypes.byref(p)))
         self.params = p
 
@@ -461,7 +483,9 @@ class Batch:
         return int(self.lib.rflbm_batch_nodes(self._h))
 
     def set_params(self, r, **kw):
-        p = make_params(self.replicas[r]["dims"], **kw)
+        """Changes the given make_params keywords of replica r; the others keep
+        their values (see merged_params)."""
+        p = merged_params(self.views[r].params, self.replicas[r]["dims"], **kw)
         check(self.lib.rflbm_batch_set_params(self._h, int(r), ctypes.byref(p)))
         self.views[r].params = p
 

@@ -158,3 +158,28 @@ int main() {{
     subprocess.run(["g++", "-O2", "-std=c++17", str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0 and out.stdout.strip() == "0"
+
+
+def test_params_round_trip_and_merge():
+    """params_kwargs reproduces a parameter set field for field; merged_params
+    changes only the keywords given (the bulk rate follows a new tau only if it
+    followed the shear rate before)."""
+    import numpy as np
+
+    dims = (8, 6, 4)
+    p = _binding.make_params(dims, storage="f16", model="bgk", kT=2e-5, tau=0.7,
+                             tau_ghost=list(np.linspace(0.6, 1.5, 17)), rho0=1.2, seed=(5 << 32) + 3,
+                             stream_id=9, philox_rounds=7, storage_scale=0.01)
+    q = _binding.make_params(dims, **_binding.params_kwargs(p))
+    assert bytes(p) == bytes(q)
+
+    m = _binding.merged_params(p, dims, kT=0.0)
+    assert m.kT == 0.0
+    assert bytes(_binding.merged_params(m, dims, kT=2e-5)) == bytes(p)
+    m = _binding.merged_params(p, dims, tau=0.9)
+    assert (m.tau_shear, m.tau_bulk) == (0.9, 0.9)
+    r = _binding.make_params(dims, tau=0.7, tau_bulk=1.0)
+    m = _binding.merged_params(r, dims, tau=0.9)
+    assert (m.tau_shear, m.tau_bulk) == (0.9, 1.0)
+    m = _binding.merged_params(r, dims, tau_bulk=0.6)
+    assert (m.tau_shear, m.tau_bulk) == (0.7, 0.6)

@@ -466,3 +466,17 @@ def test_failed_allocation_is_not_reported_again_later(rf):
         assert lib.rflbm_step_count(h) == 3
     finally:
         lib.rflbm_destroy(h)
+
+
+def test_set_params_changes_only_the_given_keywords(rf, ora):
+    """A 16-bit lattice changed with one keyword keeps its storage, rates and
+    seed (the call used to rebuild every other field from the defaults)."""
+    dims = (16, 6, 5)
+    lat = rf.Lattice(dims, storage="f16", kT=1e-4, tau=0.8, tau_bulk=1.1, seed=7, stream_id=2)
+    lat.set_populations(initial_state(ora, dims, seed=95))
+    lat.set_params(kT=2e-4)
+    p = lat.params
+    assert (p.storage, p.kT, p.tau_shear, p.tau_bulk, p.seed, p.stream_id) == (1, 2e-4, 0.8, 1.1, 7, 2)
+    lat.step(2)
+    lat.sync()
+    lat.close()
