@@ -213,6 +213,19 @@ def _before_torch(stream, device):
         cur.wait_stream(stream)
 
 
+def _field(a, device, n, rows=1):
+    """A density (rows = 1) or velocity (rows = 3) field as a contiguous FP64
+    device tensor of rows x n values; a scalar density is broadcast.  The size
+    is checked here, since the library reads rows * n values."""
+    if rows == 1 and not hasattr(a, "data_ptr"):
+        a = np.asarray(a, dtype=np.float64)
+        a = a.reshape(-1) if a.size == n else np.broadcast_to(a, (n,))
+    t = _as_device_f64(a, device)
+    if t.numel() != rows * n:
+        raise ValueError(f"field has {t.numel()} values, expected {rows} x {n}")
+    return t.reshape(rows, n) if rows > 1 else t.reshape(n)
+
+
 def _as_device_f64(a, device):
     torch = _torch()
     if isinstance(a, torch.Tensor):
@@ -296,10 +309,8 @@ class Lattice:
 
     # -- state ---------------------------------------------------------------
     def init_equilibrium(self, rho=None, u=None):
-        r = None if rho is None else _as_device_f64(np.broadcast_to(rho, (self.n,))
-                                                     if not hasattr(rho, "data_ptr") else rho,
-                                                     self.device)
-        v = None if u is None else _as_device_f64(u, self.device).reshape(3, self.n)
+        r = None if rho is None else _field(rho, self.device, self.n)
+        v = None if u is None else _field(u, self.device, self.n, rows=3)
         _after_torch(self.stream, self.device)
         check(self.lib.rflbm_init_equilibrium(self._h, None if r is None else _VP(_dev_ptr(r)),
                                               None if v is None else _VP(_dev_ptr(v)), 0))
@@ -308,10 +319,8 @@ class Lattice:
 
     def init_thermal(self, rho=None, u=None):
         """f^(0)(rho, u) plus Gaussian deviations of the stationary covariance."""
-        r = None if rho is None else _as_device_f64(np.broadcast_to(rho, (self.n,))
-                                                     if not hasattr(rho, "data_ptr") else rho,
-                                                     self.device)
-        v = None if u is None else _as_device_f64(u, self.device).reshape(3, self.n)
+        r = None if rho is None else _field(rho, self.device, self.n)
+        v = None if u is None else _field(u, self.device, self.n, rows=3)
         _after_torch(self.stream, self.device)
         check(self.lib.rflbm_init_thermal(self._h, None if r is None else _VP(_dev_ptr(r)),
                                           None if v is None else _VP(_dev_ptr(v)), 0))
@@ -534,7 +543,12 @@ def rng_normals(seed, stream_id, rounds, node0, count, t, device="cuda"):
 
 
 def copy(dst, src, nbytes, stream=None):
+    """Copies nbytes from tensor src to tensor dst with the library's copy
+    kernel (bandwidth reference); both must hold at least nbytes."""
     torch = _torch()
+    for t in (dst, src):
+        if not t.is_contiguous() or int(nbytes) > t.numel() * t.element_size():
+            raise ValueError("copy needs contiguous tensors of at least nbytes")
     s = stream if stream is not None else torch.cuda.current_stream(dst.device)
     check(load_library().rflbm_copy(_VP(_dev_ptr(dst)), _VP(_dev_ptr(src)), int(nbytes),
                                     _VP(s.cuda_stream)))

@@ -183,3 +183,21 @@ def test_params_round_trip_and_merge():
     assert (m.tau_shear, m.tau_bulk) == (0.9, 1.0)
     m = _binding.merged_params(r, dims, tau_bulk=0.6)
     assert (m.tau_shear, m.tau_bulk) == (0.7, 0.6)
+
+
+def test_field_sizes_are_checked_before_the_library_reads_them():
+    """Density and velocity fields reach the library only with N and 3 N
+    values: a scalar density is broadcast, a box-shaped one flattened, a wrong
+    size raises before any call."""
+    import numpy as np
+
+    torch = pytest.importorskip("torch")
+    n = 4 * 3 * 2
+    assert _binding._field(1.1, "cpu", n).shape == (n,)
+    assert _binding._field(np.ones((2, 3, 4)), "cpu", n).shape == (n,)
+    assert _binding._field(np.zeros((3, n)), "cpu", n, rows=3).shape == (3, n)
+    for bad, rows in ((np.ones(n + 1), 1), (torch.ones(n - 1), 1), (np.zeros((3, n - 1)), 3)):
+        with pytest.raises(ValueError):
+            _binding._field(bad, "cpu", n, rows=rows)
+    with pytest.raises(ValueError):
+        _binding.copy(torch.empty(64, dtype=torch.uint8), torch.empty(32, dtype=torch.uint8), 64)
