@@ -485,6 +485,66 @@ def profile_run(dims, storage="f32", steps=4):
     log(f"copied {nbytes} bytes")
 
 
+def profile_batch_run(storage, steps=40, graph_steps=20):
+    """The 64-replica workload in the launch shape the benchmark's autotuner
+    picks (256-node tiles, one block per tile), replayed from a captured graph
+    of graph_steps steps, for rocprofv3."""
+    import paper_2507_08820_amd as rf
+    import workloads as wl
+
+    table = wl.replica_table(64, seed=5)
+    reps = [dict(dims=t["dims"], kT=t["kT"], tau=t["tau"], seed=t["seed"], stream_id=t["stream_id"])
+            for t in table]
+    b = rf.Batch(reps, storage=storage)
+    for r, t in enumerate(table):
+        rho, u = wl.taylor_green_device(t["dims"], amp=0.01, device=b.device)
+        b[r].init_equilibrium(rho, u)
+    b.set_launch(256, 0, graph_steps)
+    b.step(graph_steps)
+    b.step(steps)
+    b.sync()
+    log(f"batch {storage}: {b.nodes} nodes, {graph_steps + steps} steps")
+    b.close()
+
+
+BATCH_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <out>/prof_batch_{s} -o trace --output-format csv "
+                   "-- python3 bench.py --profile-batch {s}")
+
+
+def summarize_batch_trace(out_dir, storage, nodes=None):
+    """profiles/batch64_<storage>_kernel_trace.txt: rocprofv3 kernel statistics
+    of the 64-replica workload (one batch_kernel launch per step for all
+    replicas) and the aggregate rate of the mean launch."""
+    import csv
+    import glob
+
+    import workloads as wl
+
+    files = glob.glob(os.path.join(out_dir, f"prof_batch_{storage}", "*kernel_stats.csv"))
+    if not files:
+        raise FileNotFoundError(f"prof_batch_{storage}")
+    with open(files[0]) as fh:
+        rows = [r for r in csv.DictReader(fh) if "batch_kernel<" in r["Name"]]
+    if nodes is None:
+        nodes = sum(int(t["dims"][0]) * int(t["dims"][1]) * int(t["dims"][2]) for t in wl.replica_table(64, seed=5))
+    path = os.path.join(ROOT, "profiles", f"batch64_{storage}_kernel_trace.txt")
+    with open(path, "w") as fh:
+        fh.write(f"# rocprofv3 kernel statistics, 64-replica batch workload ({nodes} nodes, {storage.upper()},\n")
+        fh.write("# 256-node tiles, one block per tile, graphs of 20 steps; 60 steps)\n")
+        fh.write(f"# command: {BATCH_TRACE_CMD.format(s=storage)}\n")
+        fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
+        fh.write("Name | Calls | AverageNs | MinNs | MaxNs\n")
+        for r in rows:
+            fh.write(f"{r['Name']} | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['MinNs']} | {r['MaxNs']}\n")
+        total = sum(float(r["AverageNs"]) * int(r["Calls"]) for r in rows)
+        calls = sum(int(r["Calls"]) for r in rows)
+        if calls:
+            mean = total / calls
+            fh.write(f"# mean batch step kernel: {mean:.0f} ns -> {nodes / (mean * 1e-9) / 1e6:.0f} MLUPS "
+                     f"aggregate, {BYTES_PER_UPDATE[storage] * nodes / (mean * 1e-9) / 1e9:.1f} GB/s algorithmic\n")
+    return path
+
+
 def copy_ceiling(nbytes=4 << 30, reps=20):
     import torch
 
@@ -550,6 +610,10 @@ def main():
                     help="with --table3: measured steps (400 statistics samples, 40 S(k) snapshots)")
     ap.add_argument("--profile-storage", default="f32", choices=["f32", "f16", "bf16"],
                     help="with --profile: storage of the profiled workload")
+    ap.add_argument("--profile-batch", choices=["f32", "f16"],
+                    help="run the 64-replica workload (60 graph-replayed steps) for rocprofv3")
+    ap.add_argument("--summarize-batch-trace", metavar="DIR",
+                    help="write profiles/batch64_{f32,f16}_kernel_trace.txt from the kernel-trace CSVs under DIR")
     ap.add_argument("--profile-steps", type=int, default=4,
                     help="with --profile: timed steps (2 warm-up steps up to 4, else 10)")
     ap.add_argument("--summarize-valu", metavar="DIR",
@@ -576,6 +640,13 @@ def main():
         return
     if args.profile:
         profile_run(dims, args.profile_storage, args.profile_steps)
+        return
+    if args.profile_batch:
+        profile_batch_run(args.profile_batch)
+        return
+    if args.summarize_batch_trace:
+        for storage in ("f32", "f16"):
+            print(summarize_batch_trace(args.summarize_batch_trace, storage))
         return
     if args.summarize_valu:
         for storage in ("f32", "f16"):

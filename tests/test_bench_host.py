@@ -106,3 +106,18 @@ def test_16bit_trace_summary(tmp_path, fake_root):
     n = 8 * 8 * 8
     assert f"mean step kernel: 3200 ns -> {108 * n / 3200e-9 / 1e9:.1f} GB/s" in text
     assert f"{n / 3200e-9 / 1e6:.0f} MLUPS" in text
+
+
+def test_batch_trace_summary(tmp_path, fake_root):
+    out = tmp_path / "out"
+    even = "void rflbm::(anonymous namespace)::batch_kernel<0, false, 10, true>(rflbm::BatchArgs)"
+    odd = "void rflbm::(anonymous namespace)::batch_kernel<0, true, 10, true>(rflbm::BatchArgs)"
+    stats = [dict(Name=even, Calls=30, AverageNs=800.0, MinNs=790, MaxNs=810),
+             dict(Name=odd, Calls=30, AverageNs=900.0, MinNs=890, MaxNs=910),
+             dict(Name="void rflbm::(anonymous namespace)::advance_step(unsigned int*)", Calls=60,
+                  AverageNs=2.0, MinNs=2, MaxNs=2)]
+    write_csv(str(out / "prof_batch_f32" / "trace_kernel_stats.csv"), ["Name", "Calls", "AverageNs", "MinNs", "MaxNs"], stats)
+    path = bench.summarize_batch_trace(str(out), "f32", nodes=1000)
+    text = open(path).read()
+    assert even in text and odd in text and "advance_step" not in text
+    assert f"mean batch step kernel: 850 ns -> {1000 / 850e-9 / 1e6:.0f} MLUPS" in text
