@@ -44,6 +44,11 @@ def build(verbose: bool = False) -> str:
     return _LIB_PATH
 
 
+# Collision models: Reg-FLBM (Eq. r-flbe2), BGK-FLBM (Eq. flbe), and Reg-FLBM
+# whose ghost non-equilibrium is rebuilt by the recursion of Eq. recursive_eq.
+MODELS = {"reg": 0, "bgk": 1, "rec": 2}
+
+
 class Params(ctypes.Structure):
     """Mirror of ``ora_params`` in rflbm_oracle.c."""
 
@@ -74,7 +79,7 @@ def make_params(kT=0.0, tau_shear=1.0, tau_bulk=None, tau_ghost=1.0, seed=1, str
     p.seed = seed
     p.stream_id = stream_id
     p.rounds = rounds
-    p.model = {"reg": 0, "bgk": 1}[model]
+    p.model = MODELS[model]
     return p
 
 
@@ -95,6 +100,7 @@ def _load():
     lib.ora_normals.argtypes = lib.ora_uniforms.argtypes
     lib.ora_equilibrium.argtypes = [ctypes.c_double, dp, dp]
     lib.ora_collide.argtypes = [ctypes.POINTER(Params), dp, dp, dp]
+    lib.ora_ghost_recursive.argtypes = [dp, dp, dp]
     lib.ora_step.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
                              ctypes.c_int32, ctypes.c_uint32, dp, dp, ctypes.c_int32]
     lib.ora_step.restype = ctypes.c_int
@@ -179,6 +185,17 @@ def collide(params: Params, f, r) -> np.ndarray:
     rr[:23] = np.asarray(r, dtype=np.float64)[:23]
     out = np.zeros(27)
     lib.ora_collide(ctypes.byref(params), _dp(ff), _dp(rr), _dp(out))
+    return out
+
+
+def ghost_recursive(a2, u) -> np.ndarray:
+    """Ghost non-equilibrium coefficients of modes k = 10..26 (entries 0..9 are
+    0) rebuilt by Eq. recursive_eq from a2 = (xx, yy, zz, xy, xz, yz) and u."""
+    lib = _load()
+    aa = np.ascontiguousarray(a2, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(27)
+    lib.ora_ghost_recursive(_dp(aa), _dp(uu), _dp(out))
     return out
 
 

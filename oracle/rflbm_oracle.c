@@ -25,6 +25,10 @@
  *     w_i sum_{k=4}^{26} b_k^-1 e_ki phi_k r_k of Eq. r-flbe2;
  *   - the post-collision population of Eq. r-flbe2 (Reg-FLBM) or Eq. flbe
  *     (BGK-FLBM comparator, equilibrium from Eq. hermite_feq2 as in Sec. III);
+ *   - optionally (model 2) the ghost non-equilibrium coefficients of orders
+ *     3..6 rebuilt from the second-order ones and u by the recursion of
+ *     Eq. recursive_eq, relaxed with omega_g as in Eq. r-flbe with the split
+ *     f^(1) = f^(1,h) + f^(1,g) of Sec. II.B;
  *   - push streaming f_i(x + c_i, t + 1) = f*_i(x, t) (Eq. eq:streaming) on a
  *     periodic box;
  *   - an optional thermalised start drawn from the stationary covariance
@@ -39,6 +43,10 @@
  *   - ghost modes (k >= 10) relax from their projected non-equilibrium
  *     coefficient by (1 - omega_g,k) with noise amplitude phi_k(omega_g,k);
  *     at the paper's omega_g = 1 the relaxed part vanishes as in Eq. r-flbe2;
+ *     model 2 relaxes instead the coefficient that Eq. recursive_eq rebuilds
+ *     (same noise); "perm(alpha_n)" is read as the sum over the n - 1 ways of
+ *     pairing alpha_n with one of the first n - 1 indices (the cyclic
+ *     permutations of those indices), the original term included;
  *   - the random numbers: Philox4x32-R (Salmon, Moraes, Dror and Shaw, SC'11,
  *     "Parallel random numbers: as easy as 1, 2, 3") with key (seed low word,
  *     seed high word) and counter (node, step, call j = 0..5, stream id); word
@@ -267,6 +275,35 @@ static double a0_coefficient(int k, double rho, const double u[3]) {
   return a;
 }
 
+/* Eq. recursive_eq: non-equilibrium coefficient a1^(n) of the first n indices
+ * of the Hermite index string s (n >= 2), from the second-order coefficients
+ * a2[alpha][beta] and the velocity u:
+ *   a1^(n)_{s1..sn} = a1^(n-1)_{s1..s(n-1)} u_sn
+ *                     + sum_{j < n} a2_{sj sn} prod_{l < n, l != j} u_sl,
+ * where the sum runs over the cyclic permutations of the first n - 1 indices
+ * (each of them takes the place next to s_n once). */
+static double a1_recursive(const char* s, int n, const double a2[3][3], const double u[3]) {
+  if (n == 2) return a2[axis_of(s[0])][axis_of(s[1])];
+  const int last = axis_of(s[n - 1]);
+  double r = a1_recursive(s, n - 1, a2, u) * u[last];
+  for (int j = 0; j < n - 1; ++j) {
+    double term = a2[axis_of(s[j])][last];
+    for (int l = 0; l < n - 1; ++l)
+      if (l != j) term *= u[axis_of(s[l])];
+    r += term;
+  }
+  return r;
+}
+
+/* The recursive ghost coefficients of every mode k = 10..26 (out[k]; out[0..9]
+ * are set to 0) from the six second-order coefficients a2 in Table II order
+ * (xx, yy, zz, xy, xz, yz) and u.  Exposed for the tests. */
+void ora_ghost_recursive(const double a2v[6], const double u[3], double out[NMODE]) {
+  const double a2[3][3] = {{a2v[0], a2v[3], a2v[4]}, {a2v[3], a2v[1], a2v[5]}, {a2v[4], a2v[5], a2v[2]}};
+  for (int k = 0; k < NMODE; ++k)
+    out[k] = k < 10 ? 0.0 : a1_recursive(herm_index[k], herm_order[k], a2, u);
+}
+
 void ora_equilibrium(double rho, const double u[3], double feq[NPOP]) {
   build_tables();
   double a0[NMODE];
@@ -290,7 +327,8 @@ typedef struct {
   uint64_t seed;
   uint32_t stream_id;
   uint32_t rounds;
-  int32_t model;        /* 0: Reg-FLBM (Eq. r-flbe2), 1: BGK-FLBM (Eq. flbe) */
+  int32_t model;        /* 0: Reg-FLBM (Eq. r-flbe2), 1: BGK-FLBM (Eq. flbe),
+                           2: Reg-FLBM with recursive ghosts (Eq. recursive_eq) */
   int32_t pad;
 } ora_params;
 
@@ -358,9 +396,18 @@ void ora_collide(const ora_params* p, const double f[NPOP], const double r[23], 
     relaxed[k] = (1.0 - om_s) * a1[k];
     noise_mode[k] = sqrt(mu * B[k]) * fdt_factor(om_s) * r[k - 4];
   }
+  /* Ghosts: the projected coefficient a1 (model 0), or the one Eq.
+   * recursive_eq rebuilds from the unrelaxed second-order a1 and u (model 2). */
+  double ghost_neq[NMODE];
+  if (p->model == 2) {
+    const double a2v[6] = {a1[4], a1[5], a1[6], a1[7], a1[8], a1[9]};
+    ora_ghost_recursive(a2v, u, ghost_neq);
+  } else {
+    for (int k = 0; k < NMODE; ++k) ghost_neq[k] = a1[k];
+  }
   for (int k = 10; k < NMODE; ++k) {
     const double om_g = 1.0 / p->tau_ghost[k - 10];
-    relaxed[k] = (1.0 - om_g) * a1[k];
+    relaxed[k] = (1.0 - om_g) * ghost_neq[k];
     noise_mode[k] = sqrt(mu * B[k]) * fdt_factor(om_g) * r[k - 4];
   }
 

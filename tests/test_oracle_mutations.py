@@ -4,8 +4,8 @@ Each case plants one mistake in a copy of the oracle's C source (on the CPU,
 in a scratch directory; the GPU path is not involved), rebuilds that copy and
 runs the oracle's pin tests against it: at least one pin must fail.  The
 mistakes are the kind a transcription of Table II, Eq. normal_fact,
-Eq. fluct_phi, Eq. r-flbe2, Eq. eq:streaming or of the Philox round could
-contain.  The unmutated
+Eq. fluct_phi, Eq. r-flbe2, Eq. recursive_eq, Eq. eq:streaming or of the
+Philox round could contain.  The unmutated
 copy must pass, so a failure is the mistake's doing and not the harness's.
 """
 import os
@@ -17,7 +17,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_tables.py", "tests/test_oracle_collide.py", "tests/test_oracle_dynamics.py",
-             "tests/test_philox.py"]
+             "tests/test_philox.py", "tests/test_oracle_recursive.py"]
 
 # (name, text in rflbm_oracle.c, replacement)
 MUTATIONS = [
@@ -28,7 +28,12 @@ MUTATIONS = [
     ("hermite_index_mode16", '"yyz",   "xyz",', '"yyz",   "xzz",'),
     ("fdt_omega_1_minus_omega", "sqrt(omega * (2.0 - omega))", "sqrt(omega * (1.0 - omega))"),
     ("ghost_noise_b_inverse", "sqrt(mu * B[k]) * fdt_factor(om_g)", "sqrt(mu / B[k]) * fdt_factor(om_g)"),
-    ("ghost_relaxation_sign", "relaxed[k] = (1.0 - om_g) * a1[k];", "relaxed[k] = (om_g - 1.0) * a1[k];"),
+    ("ghost_relaxation_sign", "relaxed[k] = (1.0 - om_g) * ghost_neq[k];", "relaxed[k] = (om_g - 1.0) * ghost_neq[k];"),
+    ("recursion_without_permutations", "for (int j = 0; j < n - 1; ++j) {", "for (int j = n - 2; j < n - 1; ++j) {"),
+    ("recursion_wrong_velocity", "double r = a1_recursive(s, n - 1, a2, u) * u[last];",
+     "double r = a1_recursive(s, n - 1, a2, u) * u[axis_of(s[0])];"),
+    ("recursive_ghosts_from_relaxed_a2", "const double a2v[6] = {a1[4], a1[5], a1[6], a1[7], a1[8], a1[9]};",
+     "const double a2v[6] = {(1.0 - om_s) * a1[4], a1[5], a1[6], a1[7], a1[8], a1[9]};"),
     ("trace_over_two", "(a1[4] + a1[5] + a1[6]) / 3.0;", "(a1[4] + a1[5] + a1[6]) / 2.0;"),
     ("bulk_shear_noise_swapped",
      "(fdt_factor(om_b) * r_mean + fdt_factor(om_s) * (r[k - 4] - r_mean))",
