@@ -71,8 +71,19 @@ typedef enum {
 typedef enum { RFLBM_F32 = 0, RFLBM_F16 = 1, RFLBM_BF16 = 2 } rflbm_storage;
 
 typedef enum {
-  RFLBM_MODEL_REG = 0, /* Reg-FLBM, Eq. r-flbe2 */
-  RFLBM_MODEL_BGK = 1  /* BGK-FLBM, Eq. flbe (full-Hermite equilibrium, one tau) */
+  RFLBM_MODEL_REG = 0, /* Reg-FLBM, Eq. r-flbe2; ghosts k = 10..26 relax their
+                          projected non-equilibrium m_k - m_eq,k by (1 - omega_g,k) */
+  RFLBM_MODEL_BGK = 1, /* BGK-FLBM, Eq. flbe (full-Hermite equilibrium, one tau) */
+  RFLBM_MODEL_REC = 2  /* Reg-FLBM whose ghost non-equilibrium is rebuilt from the
+                          second-order one and u by the recursion of
+                          Eq. recursive_eq (Sec. II.B), then relaxed by
+                          (1 - omega_g,k) with the noise of Eq. fluct_phi; read
+                          as the sum over index pairs
+                          a1_(s1..sn) = sum_{i<j} a1_(si sj) prod_{l != i,j} u_sl.
+                          Equal to RFLBM_MODEL_REG when every omega_g = 1; for
+                          omega_g != 1 it does not balance the ghost noise
+                          (linearised variance deficit mu b_k (1 - omega_g)^2 per
+                          ghost mode) */
 } rflbm_model;
 
 typedef struct {

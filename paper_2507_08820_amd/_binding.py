@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "rflbm.h")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
-MODEL = {"reg": 0, "bgk": 1}
+MODEL = {"reg": 0, "bgk": 1, "rec": 2}
 M_RHO, M_J, M_PI = 1, 2, 4
 FIELDS = ("rho", "jx", "jy", "jz", "pi_xx", "pi_yy", "pi_zz", "pi_xy", "pi_xz", "pi_yz")
 

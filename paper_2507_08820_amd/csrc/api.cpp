@@ -58,7 +58,8 @@ std::string validate(const rflbm_params* p) {
   if (!p) return "params is NULL";
   if (p->nx < 2 || p->ny < 2 || p->nz < 2) return "box dimensions must each be >= 2";
   if (p->storage < RFLBM_F32 || p->storage > RFLBM_BF16) return "unknown storage type";
-  if (p->model != RFLBM_MODEL_REG && p->model != RFLBM_MODEL_BGK) return "unknown model";
+  if (p->model != RFLBM_MODEL_REG && p->model != RFLBM_MODEL_BGK && p->model != RFLBM_MODEL_REC)
+    return "unknown model";
   if (p->philox_rounds != 7 && p->philox_rounds != 10) return "philox_rounds must be 7 or 10";
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return "rho0 must be positive";
   if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return "kT must be >= 0";
@@ -180,6 +181,8 @@ StepArgs step_args(const rflbm_lattice* L) {
   a.ghost_eq = 1;
   for (int k = 0; k < 17; ++k)
     if (a.lam_g[k] != 0.0f) a.ghost_eq = 0;
+  // at omega_g = 1 the relaxed ghost part vanishes in either reading
+  a.ghost_rec = (p.model == RFLBM_MODEL_REC && !a.ghost_eq) ? 1u : 0u;
   sigma_of(p, a.sigma, a.inv_sigma);
   a.flag = reinterpret_cast<int*>(L->buf + L->L.flag_off);
   a.partials = reinterpret_cast<double*>(L->buf + L->L.partial_off);

@@ -50,6 +50,8 @@ struct StepArgs {
   float amp_b_minus_s;   // sqrt(kT b_4 / cs2) (s(omega_b) - s(omega_s))
   float amp_off;         // sqrt(kT b_7 / cs2) s(omega_s), modes 7..9
   uint32_t ghost_eq;     // 1 when every omega_g,k = 1 (all lam_g = 0)
+  uint32_t ghost_rec;    // 1: ghosts relax the coefficients Eq. recursive_eq rebuilds
+                         // from the second-order ones and u (else the projected ones)
   float lam_g[17];       // 1 - omega_g,k, k = 10..26
   float amp_g[17];       // sqrt(kT b_k / cs2) s(omega_g,k)
   float sigma[4];        // storage unit per speed class (1 for FP32)

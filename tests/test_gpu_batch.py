@@ -27,6 +27,9 @@ REPLICAS = [
     dict(dims=(17, 19, 23), kT=1e-5, tau=0.55, seed=1001, stream_id=1),
     dict(dims=(32, 8, 12), kT=0.0, tau=1.2, seed=1002, stream_id=2),
     dict(dims=(9, 40, 7), kT=3e-5, tau=0.7, model="bgk", seed=1003, stream_id=3),
+    # ghosts rebuilt by the recursion of Eq. recursive_eq at omega_g != 1: the
+    # batch kernel reads the ghost setting of each replica at run time
+    dict(dims=(12, 10, 14), kT=1e-4, tau=0.9, model="rec", tau_ghost=1.3, seed=1004, stream_id=4),
 ]
 
 

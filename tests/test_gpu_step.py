@@ -77,6 +77,12 @@ CASES = {
     "rows_bgk_64x6x5": ((64, 6, 5), dict(kT=1e-4, tau=0.8, model="bgk", seed=18)),
     "rows_philox7_256x2x3": ((256, 2, 3), dict(kT=1e-4, tau=0.9, philox_rounds=7, seed=(3 << 32) + 19,
                                                 stream_id=5)),
+    # ghosts rebuilt by the recursion of Eq. recursive_eq, omega_g != 1, on the
+    # tiled kernels and on the row-aligned ones
+    "rec_17x19x23": ((17, 19, 23), dict(kT=1e-4, tau=0.7, tau_bulk=1.2, model="rec",
+                                        tau_ghost=list(np.linspace(0.55, 1.9, 17)), seed=20)),
+    "rows_rec_128x5x3": ((128, 5, 3), dict(kT=1e-4, tau=0.6, model="rec", tau_ghost=0.8, seed=21)),
+    "rec_kT0_33x7x6": ((33, 7, 6), dict(kT=0.0, tau=0.9, model="rec", tau_ghost=1.5)),
 }
 
 
