@@ -192,6 +192,21 @@ rflbm_status rflbm_set_populations(rflbm_lattice* lat, const double* src, int sr
 #define RFLBM_M_PI 4u
 rflbm_status rflbm_get_moments(rflbm_lattice* lat, uint32_t mask, float* dst, int dst_is_host);
 
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc, code around HIP graph captures): the fields of
+ * rflbm_get_moments (same mask, same planar layout, bit for bit the same
+ * values) into HOST memory dst, which the caller owns and sizes to
+ * (number of selected fields) * N floats.  rflbm_get_moments with a host dst
+ * stages the fields in a device buffer of the whole field size that it
+ * allocates per call; this call allocates nothing: the fields pass through a
+ * fixed 8 MiB device array that the library holds on each GPU it runs on until
+ * the process ends, in chunks of at most 8 MiB, so every box size is served.
+ * Runs on the lattice's stream and waits for it before returning.  Calls on
+ * one GPU share that array and are serialised by the library (one at a time
+ * per GPU in a process).  EINVAL for a NULL lattice or dst or a bad mask; EHIP
+ * if a kernel or copy fails (dst then partly written). */
+rflbm_status rflbm_get_moments_host_noalloc(rflbm_lattice* lat, uint32_t mask, float* dst);
+
 /* Ensemble statistics of Sec. III (equilibration ratios), accumulated on the
  * GPU in FP64 inside the step kernel on every step whose count t is a multiple
  * of `every` (sampled before that step's collision).  Sums run over sampled

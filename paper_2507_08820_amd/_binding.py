@@ -84,6 +84,7 @@ _SIGS = {
     "rflbm_set_populations": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     "rflbm_get_populations_at": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP]),
     "rflbm_get_moments": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, ctypes.c_int]),
+    "rflbm_get_moments_host_noalloc": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP]),
     "rflbm_stats_config": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "rflbm_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(Stats)]),
     "rflbm_reset_stats": (ctypes.c_int, [_VP]),
@@ -364,6 +365,16 @@ class Lattice:
         _after_torch(self.stream, self.device)
         check(self.lib.rflbm_get_moments(self._h, mask, _VP(_dev_ptr(out)), 0))
         _before_torch(self.stream, self.device)
+        return out
+
+    def moments_host_noalloc(self, mask=M_RHO | M_J | M_PI):
+        """The moment fields as a host (numpy) array, staged through the
+        library's fixed device array: no device memory is allocated."""
+        import numpy as np
+        nf = (1 if mask & M_RHO else 0) + (3 if mask & M_J else 0) + (6 if mask & M_PI else 0)
+        out = np.empty((nf, self.n), dtype=np.float32)
+        _after_torch(self.stream, self.device)
+        check(self.lib.rflbm_get_moments_host_noalloc(self._h, mask, _VP(out.ctypes.data)))
         return out
 
     # -- stepping --------------------------------------------------------------

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librflbm.so")
-SOURCES = ["step.hip", "aux.hip", "sk.hip", "api.cpp", "batch.cpp"]
+SOURCES = ["step.hip", "aux.hip", "sk.hip", "noalloc.hip", "api.cpp", "batch.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

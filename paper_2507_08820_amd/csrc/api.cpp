@@ -124,6 +124,10 @@ void sigma_of(const rflbm_params& p, float sigma[4], float inv[4]) {
   }
 }
 
+}  // namespace
+
+namespace rflbm {
+
 GatherArgs gather_args(const rflbm_lattice* L, const rflbm_params& p, int64_t t) {
   GatherArgs g;
   g.pop = L->buf;
@@ -139,7 +143,7 @@ GatherArgs gather_args(const rflbm_lattice* L, const rflbm_params& p, int64_t t)
   return g;
 }
 
-}  // namespace
+}  // namespace rflbm
 
 namespace rflbm {
 
@@ -194,6 +198,10 @@ void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStre
   L->L = layout_for(p);
   L->buf = buf;
   L->stream = s;
+  if (hipGetDevice(&L->device) != hipSuccess) {
+    (void)hipGetLastError();
+    L->device = 0;
+  }
   L->launch = make_launch(p.nx, p.ny, p.nz, p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64),
                           p.nx >= 256 ? 1 : (p.nx >= 128 ? 2 : 4));
   L->row_mode = true;

@@ -187,34 +187,36 @@ __global__ void init_thermal_kernel(const GatherArgs g, const double* rho, const
   }
 }
 
+// Moment fields of the nodes n0 .. n0 + count - 1: field c of node n0 + k goes
+// to dst[c * pitch + k].
 template <int S>
-__global__ void moments_kernel(const GatherArgs g, uint32_t mask, float* dst) {
+__global__ void moments_kernel(const GatherArgs g, uint32_t mask, uint64_t n0, uint64_t count,
+                               uint64_t pitch, float* dst) {
   using C = Codec<S>;
   using T = typename C::T;
-  const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
   const T* pop = static_cast<const T*>(g.pop);
-  for (uint64_t n = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; n < N;
-       n += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const NodeXYZ p = coords(n, g.nx, g.ny);
+  for (uint64_t k = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; k < count;
+       k += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const NodeXYZ p = coords(n0 + k, g.nx, g.ny);
     float v[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) v[i] = C::decode(pop[slot_index(i, p, g)], g.sigma[speed_class(i)]);
     forward27(v);
     float* out = dst;
     if (mask & 1u) {
-      out[n] = static_cast<float>(g.rho0 + static_cast<double>(v[0]));
-      out += N;
+      out[k] = static_cast<float>(g.rho0 + static_cast<double>(v[0]));
+      out += pitch;
     }
     if (mask & 2u) {
-      out[n] = v[1];
-      out[N + n] = v[3];
-      out[2 * N + n] = v[9];
-      out += 3 * N;
+      out[k] = v[1];
+      out[pitch + k] = v[3];
+      out[2 * pitch + k] = v[9];
+      out += 3 * pitch;
     }
     if (mask & 4u) {
       const int slots[6] = {mode_slot(4), mode_slot(5), mode_slot(6), mode_slot(7), mode_slot(8), mode_slot(9)};
 #pragma unroll
-      for (int c = 0; c < 6; ++c) out[c * N + n] = v[slots[c]];
+      for (int c = 0; c < 6; ++c) out[c * pitch + k] = v[slots[c]];
     }
   }
 }
@@ -415,7 +417,14 @@ hipError_t launch_init_thermal(int storage, const GatherArgs& g, const double* r
 hipError_t launch_get_moments(int storage, const GatherArgs& g, uint32_t mask, float* dst,
                               hipStream_t s) {
   const uint64_t N = static_cast<uint64_t>(g.nx) * g.ny * g.nz;
-  RFLBM_DISPATCH_STORAGE(storage, moments_kernel, dim3(grid_for(N, 256)), dim3(256), s, g, mask, dst);
+  return launch_get_moments_range(storage, g, mask, 0, N, dst, N, s);
+}
+
+hipError_t launch_get_moments_range(int storage, const GatherArgs& g, uint32_t mask, uint64_t n0,
+                                    uint64_t count, float* dst, uint64_t pitch, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  RFLBM_DISPATCH_STORAGE(storage, moments_kernel, dim3(grid_for(count, 256)), dim3(256), s, g, mask, n0,
+                         count, pitch, dst);
   return hipGetLastError();
 }
 

@@ -144,6 +144,10 @@ hipError_t launch_init_thermal(int storage, const GatherArgs& g, const double* r
 // Moment fields (FP32, planar) selected by mask (1 rho, 2 j, 4 Pi).
 hipError_t launch_get_moments(int storage, const GatherArgs& g, uint32_t mask, float* dst,
                               hipStream_t s);
+// The same fields for the nodes n0 .. n0 + count - 1 only: field c of node
+// n0 + k -> dst[c * pitch + k] (bit for bit the values of launch_get_moments).
+hipError_t launch_get_moments_range(int storage, const GatherArgs& g, uint32_t mask, uint64_t n0,
+                                    uint64_t count, float* dst, uint64_t pitch, hipStream_t s);
 // Re-encodes stored deviations after a change of rho0 or sigma.
 hipError_t launch_reencode(int storage, const GatherArgs& from, const GatherArgs& to,
                            hipStream_t s);

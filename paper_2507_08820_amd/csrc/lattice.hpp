@@ -57,6 +57,7 @@ struct rflbm_lattice {
   bool owns_buf = false;
   bool is_view = false;  // a replica of a batch (borrowed, destroyed with the batch)
   hipStream_t stream = nullptr;
+  int device = 0;  // HIP device current when the lattice was set up
   int64_t t = 0;
   int32_t stats_every = 0;
   rflbm::Launch launch{};
@@ -80,6 +81,9 @@ namespace rflbm {
 
 // Kernel arguments of one step of lattice L (everything but the step count).
 StepArgs step_args(const rflbm_lattice* L);
+// Arguments of the readback and set-up kernels for lattice L with parameters p
+// at step count t (the parity of t selects the AA layout).
+GatherArgs gather_args(const rflbm_lattice* L, const rflbm_params& p, int64_t t);
 // Sets up a lattice object on an existing buffer (no allocation, no kernels).
 void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStream_t s);
 // Zeroes the populations (rest state), flag and accumulators of L.
