@@ -25,23 +25,38 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rflbm_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# RFLBM_ORACLE_LIBRARY names another build of the same source (the
+# sanitizer build of the CPU tests); it is loaded as is, never rebuilt here.
+_LIB_OVERRIDE = os.environ.get("RFLBM_ORACLE_LIBRARY")
+_LIB_PATH = _LIB_OVERRIDE or os.path.join(_HERE, "liboracle.so")
 _lib = None
+# clang, whose AddressSanitizer runtime is the one the HIP toolchain also ships
+SANITIZE_CC = "/opt/rocm/llvm/bin/clang"
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined",
+                  "-shared-libsan", "-g"]
 
 CS2 = 1.0 / 3.0
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (OpenMP).  Always recompiles."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", _LIB_PATH + ".tmp",
-           _SRC, "-lm"]
+def build(verbose: bool = False, sanitize: bool = False, out: str | None = None) -> str:
+    """Compile the oracle with gcc (OpenMP).  Always recompiles.  sanitize:
+    AddressSanitizer and UndefinedBehaviorSanitizer build with clang into
+    `out` (load it with clang's ASan runtime preloaded)."""
+    out = out or os.path.join(_HERE, "liboracle.so")
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    if sanitize:
+        cmd = [SANITIZE_CC, "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", *SANITIZE_FLAGS,
+               "-o", out + ".tmp", _SRC, "-lm"]
+    else:
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", out + ".tmp", _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)
-    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    os.replace(out + ".tmp", out)
     global _lib
-    _lib = None
-    return _LIB_PATH
+    if out == _LIB_PATH:
+        _lib = None
+    return out
 
 
 # Collision models: Reg-FLBM (Eq. r-flbe2), BGK-FLBM (Eq. flbe), and Reg-FLBM
@@ -87,7 +102,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    if not _LIB_OVERRIDE and (not os.path.exists(_LIB_PATH)
+                              or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
         build()
     lib = ctypes.CDLL(_LIB_PATH)
     dp = ctypes.POINTER(ctypes.c_double)

@@ -37,8 +37,18 @@ def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
     return obj
 
 
-def build(verbose: bool = False, extra_flags=(), out: str = LIB, build_dir: str = BUILD) -> str:
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host code only (the C
+# interface, batch and run-time logic); device code is built as usual.  The
+# library is then loaded with clang's ASan runtime preloaded.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-g"]
+
+
+def build(verbose: bool = False, extra_flags=(), out: str = LIB, build_dir: str = BUILD,
+          sanitize_host: bool = False) -> str:
     """Compiles every source and links `out`; extra_flags go to every hipcc call."""
+    if sanitize_host:
+        extra_flags = (*extra_flags, *HOST_SANITIZE)
     os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir, tuple(extra_flags)), SOURCES))
