@@ -112,7 +112,9 @@ void rflbm_params_default(rflbm_params* p, int32_t nx, int32_t ny, int32_t nz);
  * statistics partials, flags), or 0 if the parameters are invalid. */
 size_t rflbm_required_bytes(const rflbm_params* p);
 
-/* Creates a lattice.  dev_buf: device memory of at least
+/* Creates a lattice: the periodic box and the parameters of the update of
+ * Sec. II (tau_h, omega_g, k_BT of Eq. fluct_phi) and of the validation runs
+ * of Sec. III (cubic periodic box, rho normalised to rho0).  dev_buf: device memory of at least
  * rflbm_required_bytes(p) bytes that the caller owns and keeps alive until
  * rflbm_destroy (the library never frees it), or NULL to let the library
  * allocate it.  hip_stream: a hipStream_t or NULL.  The populations start at
@@ -125,8 +127,9 @@ rflbm_status rflbm_create(const rflbm_params* p, void* dev_buf, size_t bytes, vo
  * the library allocated it).  NULL is accepted. */
 rflbm_status rflbm_destroy(rflbm_lattice* lat);
 
-/* Replaces the physical parameters (model, rounds, rho0, kT, taus, seed,
- * stream id, storage scale).  Box size and storage type must not change
+/* Replaces the physical parameters of the update of Sec. II (model, tau_h
+ * and omega_g of Eq. r-flbe2, k_BT of Eq. fluct_phi, rho0 of Sec. III) and of
+ * the noise source (rounds, seed, stream id), and the storage scale.  Box size and storage type must not change
  * (EINVAL).  Changing rho0 or the 16-bit storage scale re-encodes the stored
  * populations so that the state f is kept. */
 rflbm_status rflbm_set_params(rflbm_lattice* lat, const rflbm_params* p);
@@ -153,14 +156,16 @@ rflbm_status rflbm_init_thermal(rflbm_lattice* lat, const double* rho, const dou
  * reported by the next rflbm_sync. */
 rflbm_status rflbm_step(rflbm_lattice* lat, int64_t nsteps);
 
-/* Waits for the lattice stream.  Returns EUNSTABLE if any node of any step so
+/* Build addition (no passage of the paper defines it): waits for the lattice
+ * stream.  Returns EUNSTABLE if any node of any step so
  * far saw rho <= 0 or a non-finite density or momentum (the flag is sticky
  * until the populations are set again). */
 rflbm_status rflbm_sync(rflbm_lattice* lat);
 
-/* Steps taken so far (the time t of the current state). */
+/* Steps taken so far: the time t of the state f(x, t) of Eq. eq:streaming,
+ * which is also the step word of the noise counter. */
 int64_t rflbm_step_count(const rflbm_lattice* lat);
-/* Sets t (checkpoint restart: set_populations + set_step_count resumes a run
+/* Sets the time t of Eq. eq:streaming (checkpoint restart: set_populations + set_step_count resumes a run
  * bit for bit, since the noise depends only on (seed, n, t, stream_id)).  A
  * change of parity moves the stored state to the other AA layout in place and
  * bit for bit, with a temporary device buffer of one population plane
@@ -169,8 +174,9 @@ int64_t rflbm_step_count(const rflbm_lattice* lat);
  * stored populations are undefined until they are set again. */
 rflbm_status rflbm_set_step_count(rflbm_lattice* lat, int64_t t);
 
-/* Reads the populations f(x, t) (FP64, planar, 27 N values) into dst.  With a
- * host dst the call waits for the stream. */
+/* Reads the pre-collision populations f_i(x, t) of Eq. eq:streaming (the
+ * state after t complete steps; Table I velocity order as above; FP64, planar,
+ * 27 N values) into dst.  With a host dst the call waits for the stream. */
 rflbm_status rflbm_get_populations(rflbm_lattice* lat, double* dst, int dst_is_host);
 /* Reads f(x, t) at `count` nodes only: nodes[k] (device array of node indices
  * n < N) -> dst[i * count + k] (device, FP64, 27 * count values).  For
@@ -178,8 +184,8 @@ rflbm_status rflbm_get_populations(rflbm_lattice* lat, double* dst, int dst_is_h
  * n >= N reads nothing and yields NaN for its 27 values. */
 rflbm_status rflbm_get_populations_at(rflbm_lattice* lat, const uint32_t* nodes, uint32_t count,
                                       double* dst);
-/* Writes the populations f(x, t) from src (FP64, planar, 27 N values); clears
- * the instability flag. */
+/* Writes the pre-collision populations f_i(x, t) of Eq. eq:streaming from src
+ * (FP64, planar, 27 N values); clears the instability flag. */
 rflbm_status rflbm_set_populations(rflbm_lattice* lat, const double* src, int src_is_host);
 
 /* Moment fields of the current state, FP32, planar.  mask selects fields in
@@ -298,9 +304,10 @@ rflbm_status rflbm_batch_create(int32_t n, const rflbm_params* p, void* dev_buf,
 rflbm_status rflbm_batch_destroy(rflbm_batch* b);
 /* Borrowed view of replica r: every rflbm_* lattice call that reads or writes
  * state works on it (populations, moments, S(k), init, set_populations,
- * statistics configuration); stepping, re-timing and parameter changes go
- * through the batch (the lattice calls return ESTATE on a view).  The view
- * lives as long as the batch; rflbm_destroy on it returns ESTATE. */
+ * statistics readback and reset); stepping, re-timing, parameter changes and
+ * the statistics schedule go through the batch (the lattice calls return
+ * ESTATE on a view).  The view lives as long as the batch; rflbm_destroy on it
+ * returns ESTATE. */
 rflbm_status rflbm_batch_lattice(rflbm_batch* b, int32_t r, rflbm_lattice** view);
 /* Replaces the parameters of replica r (same rules as rflbm_set_params). */
 rflbm_status rflbm_batch_set_params(rflbm_batch* b, int32_t r, const rflbm_params* p);
@@ -314,8 +321,19 @@ rflbm_status rflbm_batch_step_separate(rflbm_batch* b, int64_t nsteps);
 /* Waits; EUNSTABLE if any replica's instability flag is set. */
 rflbm_status rflbm_batch_sync(rflbm_batch* b);
 int64_t rflbm_batch_step_count(const rflbm_batch* b);
-/* Sets t for every replica (checkpoint restart of a batch). */
+/* Sets t for every replica (checkpoint restart of a batch).  A change of parity
+ * takes one temporary population plane of the largest replica, allocated
+ * before any replica moves: ENOMEM leaves the batch unchanged. */
 rflbm_status rflbm_batch_set_step_count(rflbm_batch* b, int64_t t);
+/* The ensemble statistics of rflbm_stats_config (Sec. III, equilibration
+ * ratios) for every replica of the batch: sampled by the batched step on every
+ * step whose count t is a multiple of `every` (0: off), before that step's
+ * collision, into each replica's own accumulators (read with rflbm_get_stats
+ * on its view).  Per-tile FP64 partials are summed in a fixed order, so the
+ * sums are reproducible bit for bit for a given tile size (which sets that
+ * order); across tile sizes, and against a stand-alone lattice, they agree to
+ * FP64 rounding. */
+rflbm_status rflbm_batch_stats_config(rflbm_batch* b, int32_t every);
 /* Total nodes over all replicas. */
 int64_t rflbm_batch_nodes(const rflbm_batch* b);
 /* Launch shape: tile = nodes per work item (128 or 256, one thread per node),
@@ -329,11 +347,13 @@ rflbm_status rflbm_batch_get_launch(const rflbm_batch* b, int32_t* tile, int32_t
 /* Times nsteps batch steps with HIP events on the batch stream. */
 rflbm_status rflbm_batch_time_steps(rflbm_batch* b, int64_t nsteps, double* ms);
 /* Picks the fastest launch shape by timing trial_steps (even) steps of each
- * candidate (tile 128/256 x blocks per CU 0/2/4/8/16); the trial steps are
- * ordinary steps of the simulation.  With a cache_path (text file, one line
- * per batch signature: device, storage, rounds, replica boxes), a cached choice
- * is applied without timing and new choices are appended.  The graph length is
- * kept. */
+ * candidate (tile 128/256 x blocks per CU 0/2/4/8/16).  The trials run on the
+ * batch's own state, which is copied aside first (device memory for one copy
+ * of every replica region, ENOMEM if that is not available) and restored with
+ * the step count afterwards, so the simulation continues bit for bit as if
+ * untuned.  With a cache_path (text file, one line per batch signature:
+ * device, storage, rounds, replica boxes), a cached choice is applied without
+ * timing and new choices are appended.  The graph length is kept. */
 rflbm_status rflbm_batch_autotune(rflbm_batch* b, int32_t trial_steps, const char* cache_path);
 
 /* Diagnostics.

@@ -109,6 +109,7 @@ _SIGS = {
     "rflbm_batch_sync": (ctypes.c_int, [_VP]),
     "rflbm_batch_step_count": (ctypes.c_int64, [_VP]),
     "rflbm_batch_set_step_count": (ctypes.c_int, [_VP, ctypes.c_int64]),
+    "rflbm_batch_stats_config": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "rflbm_batch_nodes": (ctypes.c_int64, [_VP]),
     "rflbm_batch_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "rflbm_batch_get_launch": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32),
@@ -214,16 +215,25 @@ def _before_torch(stream, device):
         cur.wait_stream(stream)
 
 
-def _field(a, device, n, rows=1):
+def _field(a, device, dims, rows=1):
     """A density (rows = 1) or velocity (rows = 3) field as a contiguous FP64
-    device tensor of rows x n values; a scalar density is broadcast.  The size
-    is checked here, since the library reads rows * n values."""
-    if rows == 1 and not hasattr(a, "data_ptr"):
-        a = np.asarray(a, dtype=np.float64)
-        a = a.reshape(-1) if a.size == n else np.broadcast_to(a, (n,))
+    device tensor of rows x N values, N = nx ny nz, in the library's node
+    order n = x + nx (y + ny z).  Accepted shapes: (N,) or (nz, ny, nx) for a
+    density (a scalar is broadcast), (3, N) or (3, nz, ny, nx) for a velocity
+    (component first); a box-shaped array is indexed [z, y, x], so its
+    flattening is the node order.  Any other shape raises ValueError before the
+    library reads rows * N values."""
+    nx, ny, nz = (int(d) for d in dims)
+    n = nx * ny * nz
+    if rows == 1 and not hasattr(a, "data_ptr") and np.ndim(a) == 0:
+        a = np.full(n, float(a))
+    shape = tuple(a.shape) if hasattr(a, "shape") else np.shape(a)
+    box = (nz, ny, nx)
+    allowed = {(n,), box} if rows == 1 else {(3, n), (3,) + box}
+    if shape not in allowed:
+        raise ValueError(f"field of shape {shape}; expected one of {sorted(allowed)} "
+                         f"(box-shaped fields are indexed [z, y, x])")
     t = _as_device_f64(a, device)
-    if t.numel() != rows * n:
-        raise ValueError(f"field has {t.numel()} values, expected {rows} x {n}")
     return t.reshape(rows, n) if rows > 1 else t.reshape(n)
 
 
@@ -310,8 +320,8 @@ class Lattice:
 
     # -- state ---------------------------------------------------------------
     def init_equilibrium(self, rho=None, u=None):
-        r = None if rho is None else _field(rho, self.device, self.n)
-        v = None if u is None else _field(u, self.device, self.n, rows=3)
+        r = None if rho is None else _field(rho, self.device, self.dims)
+        v = None if u is None else _field(u, self.device, self.dims, rows=3)
         _after_torch(self.stream, self.device)
         check(self.lib.rflbm_init_equilibrium(self._h, None if r is None else _VP(_dev_ptr(r)),
                                               None if v is None else _VP(_dev_ptr(v)), 0))
@@ -320,8 +330,8 @@ class Lattice:
 
     def init_thermal(self, rho=None, u=None):
         """f^(0)(rho, u) plus Gaussian deviations of the stationary covariance."""
-        r = None if rho is None else _field(rho, self.device, self.n)
-        v = None if u is None else _field(u, self.device, self.n, rows=3)
+        r = None if rho is None else _field(rho, self.device, self.dims)
+        v = None if u is None else _field(u, self.device, self.dims, rows=3)
         _after_torch(self.stream, self.device)
         check(self.lib.rflbm_init_thermal(self._h, None if r is None else _VP(_dev_ptr(r)),
                                           None if v is None else _VP(_dev_ptr(v)), 0))
@@ -517,6 +527,11 @@ class Batch:
 
     def sync(self):
         check(self.lib.rflbm_batch_sync(self._h))
+
+    def stats_config(self, every):
+        """Statistics of every replica on every `every`-th step (0: off); read
+        them with stats() on a replica view."""
+        check(self.lib.rflbm_batch_stats_config(self._h, int(every)))
 
     def set_launch(self, tile=256, blocks_per_cu=8, graph_steps=0):
         check(self.lib.rflbm_batch_set_launch(self._h, int(tile), int(blocks_per_cu),

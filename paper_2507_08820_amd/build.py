@@ -20,6 +20,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-munsafe-fp-atomics",
+    # multiply-adds only where the source writes them (fmaf, or a * b + c in one
+    # expression): every kernel that expands the node body then rounds alike, so
+    # the row-aligned, tiled and batched steps store the same bits
+    "-ffp-contract=on",
     # packed FP32 instructions stay off (see the design notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

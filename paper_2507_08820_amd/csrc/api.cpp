@@ -174,13 +174,17 @@ StepArgs step_args(const rflbm_lattice* L) {
   // phi_k = sqrt(rho) sqrt(kT b_k / cs2) sqrt(omega_k (2 - omega_k))  (Eq. fluct_phi)
   const double kt = p.kT;
   const double base4 = std::sqrt(kt * mode_norm(4) / kCs2);
-  a.amp_s = static_cast<float>(base4 * fdt(om_s));
-  a.amp_b_minus_s = static_cast<float>(base4 * (fdt(om_b) - fdt(om_s)));
-  a.amp_off = static_cast<float>(std::sqrt(kt * mode_norm(7) / kCs2) * fdt(om_s));
+  // the step kernels carry mode k pre-multiplied by inv_scale of its register
+  // slot (the scaled inverse transform), so its noise amplitude carries it too
+  // (xx, yy, zz share one scale, as do xy, xz, yz)
+  a.amp_s = static_cast<float>(inv_scale(mode_slot(4)) * base4 * fdt(om_s));
+  a.amp_b_minus_s = static_cast<float>(inv_scale(mode_slot(4)) * base4 * (fdt(om_b) - fdt(om_s)));
+  a.amp_off = static_cast<float>(inv_scale(mode_slot(7)) * std::sqrt(kt * mode_norm(7) / kCs2) * fdt(om_s));
   for (int k = 10; k < 27; ++k) {
     const double om_g = bgk ? om_s : 1.0 / p.tau_ghost[k - 10];
     a.lam_g[k - 10] = static_cast<float>(1.0 - om_g);
-    a.amp_g[k - 10] = static_cast<float>(std::sqrt(kt * mode_norm(k) / kCs2) * fdt(om_g));
+    a.amp_g[k - 10] =
+        static_cast<float>(inv_scale(mode_slot(k)) * std::sqrt(kt * mode_norm(k) / kCs2) * fdt(om_g));
   }
   a.ghost_eq = 1;
   for (int k = 0; k < 17; ++k)
@@ -304,34 +308,46 @@ rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps) {
     const bool stats = L->stats_every > 0 && (t % L->stats_every) == 0;
     a.step = static_cast<uint32_t>(t & 0xffffffffu);
     const bool odd = (t & 1) != 0;
-    if (odd && !stats && odd_in_rows(L))
-      RFLBM_HIP(launch_step_row(L->p.storage, rounds, a, L->stream));
-    else if (!odd && !stats && rows_pay(L) && L->p.nx % 64 == 0)
+    uint32_t grid = L->launch.grid;  // blocks, hence statistics partials, of the kernel used
+    if (odd && odd_in_rows(L)) {
+      RFLBM_HIP(launch_step_row(L->p.storage, rounds, stats, a, L->stream));
+      grid = row_grid(L->p.ny, L->p.nz);
+    } else if (!odd && !stats && rows_pay(L) && L->p.nx % 64 == 0) {
       RFLBM_HIP(launch_step_wave(L->p.storage, rounds, a, L->stream));
-    else
+    } else {
       RFLBM_HIP(launch_step(L->p.storage, odd, rounds, stats, a, L->launch, L->stream));
-    if (stats) RFLBM_HIP(launch_stats_reduce(a.partials, L->launch.grid, scratch, acc, L->stream));
+    }
+    if (stats) RFLBM_HIP(launch_stats_reduce(a.partials, grid, scratch, acc, L->stream));
     L->t = t + 1;
   }
   return RFLBM_OK;
 }
 
-rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t) {
+size_t parity_scratch_bytes(const rflbm_lattice* L) { return nodes(L) * storage_bytes(L->p.storage); }
+
+rflbm_status lattice_set_step_count_with(rflbm_lattice* L, int64_t t, void* tmp) {
   if (t < 0) return fail(RFLBM_EINVAL, "step count must be >= 0");
   if ((t & 1) != (L->t & 1)) {
     // the storage layout depends on the parity: move the state to the new one,
     // in place and bit for bit, through one population plane of scratch
-    const uint64_t N = nodes(L);
-    void* tmp = nullptr;
-    if (const hipError_t m = hipMalloc(&tmp, N * storage_bytes(L->p.storage)); m != hipSuccess)
-      return hip_fail(RFLBM_ENOMEM, "re-layout scratch", m);
     hipError_t e = launch_swap_parity(L->p.storage, gather_args(L, L->p, L->t), tmp, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(RFLBM_EHIP, "re-layout", e);
   }
   L->t = t;
   return RFLBM_OK;
+}
+
+rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t) {
+  if (t < 0) return fail(RFLBM_EINVAL, "step count must be >= 0");
+  void* tmp = nullptr;
+  if ((t & 1) != (L->t & 1)) {
+    if (const hipError_t m = hipMalloc(&tmp, parity_scratch_bytes(L)); m != hipSuccess)
+      return hip_fail(RFLBM_ENOMEM, "re-layout scratch", m);
+  }
+  const rflbm_status st = lattice_set_step_count_with(L, t, tmp);
+  if (tmp) (void)hipFree(tmp);
+  return st;
 }
 
 }  // namespace rflbm
@@ -539,6 +555,8 @@ rflbm_status rflbm_get_moments(rflbm_lattice* L, uint32_t mask, float* dst, int 
 
 rflbm_status rflbm_stats_config(rflbm_lattice* L, int32_t every) {
   if (rflbm_status s = check_lattice(L)) return s;
+  if (L->is_view)
+    return fail(RFLBM_ESTATE, "statistics of batch replicas are configured with rflbm_batch_stats_config");
   if (every < 0) return fail(RFLBM_EINVAL, "every must be >= 0");
   L->stats_every = every;
   return RFLBM_OK;

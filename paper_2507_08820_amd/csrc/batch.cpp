@@ -7,10 +7,11 @@
 // stand-alone lattice (populations, flag, accumulators, partials), so a
 // borrowed per-replica view supports every single-lattice call (readback,
 // moments, S(k), set_populations).  After the replica regions come the batch
-// tables: one ReplicaArgs per replica, the replica of each tile, and the device
-// step counter read by the kernel.
+// tables: one ReplicaArgs per replica, the replica of each tile, the device
+// step counter read by the kernel, and the per-tile statistics partials.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -33,7 +34,7 @@ constexpr int32_t kBpcChoices[5] = {0, 2, 4, 8, 16};
 
 struct BatchLayout {
   std::vector<size_t> region_off;  // byte offset of each replica region
-  size_t reps_off, tiles_off, step_off, total;
+  size_t reps_off, tiles_off, step_off, partials_off, total;
   uint32_t max_tiles;              // tile-table capacity (smallest tile size)
 };
 
@@ -53,6 +54,8 @@ BatchLayout batch_layout(int32_t n, const rflbm_params* p) {
   off += align_up(static_cast<size_t>(B.max_tiles) * sizeof(uint32_t), kAlign);
   B.step_off = off;
   off += kAlign;
+  B.partials_off = off;
+  off += align_up(static_cast<size_t>(kNumStats) * B.max_tiles * sizeof(double), kAlign);
   B.total = off;
   return B;
 }
@@ -85,6 +88,8 @@ struct rflbm_batch {
   hipStream_t stream = nullptr;
   std::vector<rflbm_lattice*> views;
   int64_t t = 0;
+  uint32_t dev_step = 0;   // value of the device step counter once queued work has run
+  int32_t stats_every = 0; // statistics every that many steps (0: off), all replicas
   int rounds = 0;          // Philox rounds of the kernel, 0 if every kT is 0
   uint32_t tile = 256;     // nodes per tile = threads per block
   int32_t bpc = 8;         // persistent blocks per CU (0: one block per tile)
@@ -95,6 +100,7 @@ struct rflbm_batch {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int32_t exec_steps = 0;  // steps captured in exec
+  int64_t exec_phase = 0;  // t mod stats_every at the first captured step
 };
 
 namespace {
@@ -128,6 +134,7 @@ rflbm_status upload_tables(rflbm_batch* b) {
     ra.tile0 = t0;
     ra.div_x = make_fastdiv(static_cast<uint32_t>(p.nx));
     ra.div_xy = make_fastdiv(static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny));
+    ra.acc = reinterpret_cast<double*>(b->views[r]->buf + b->views[r]->L.acc_off);
     const uint32_t nt = (ra.nodes + b->tile - 1) / b->tile;
     for (uint32_t k = 0; k < nt; ++k) tile_rep.push_back(static_cast<uint32_t>(r));
     t0 += nt;
@@ -143,14 +150,21 @@ rflbm_status upload_tables(rflbm_batch* b) {
   return RFLBM_OK;
 }
 
-BatchArgs batch_args(const rflbm_batch* b) {
+BatchArgs batch_args(const rflbm_batch* b, uint32_t step_offset) {
   BatchArgs a;
   a.reps = reinterpret_cast<const ReplicaArgs*>(b->buf + b->B.reps_off);
   a.tile_rep = reinterpret_cast<const uint32_t*>(b->buf + b->B.tiles_off);
   a.ntiles = b->ntiles;
   a.step = reinterpret_cast<const uint32_t*>(b->buf + b->B.step_off);
+  a.step_offset = step_offset;
+  a.partial_pitch = b->B.max_tiles;
+  a.partials = reinterpret_cast<double*>(b->buf + b->B.partials_off);
   return a;
 }
+
+uint32_t* step_counter(rflbm_batch* b) { return reinterpret_cast<uint32_t*>(b->buf + b->B.step_off); }
+
+bool stats_step(const rflbm_batch* b, int64_t t) { return b->stats_every > 0 && t % b->stats_every == 0; }
 
 uint32_t batch_grid(const rflbm_batch* b) {
   if (b->bpc <= 0) return b->ntiles;
@@ -158,21 +172,29 @@ uint32_t batch_grid(const rflbm_batch* b) {
   return static_cast<uint32_t>(g < b->ntiles ? g : b->ntiles);
 }
 
-// Enqueues one step of parity (t & 1) plus the device counter update.
-hipError_t enqueue_step(rflbm_batch* b, bool odd, hipStream_t s) {
-  const BatchArgs a = batch_args(b);
-  hipError_t e = launch_batch_step(b->p[0].storage, odd, b->rounds, b->all_ghost_eq, a, batch_grid(b), b->tile, s);
-  if (e != hipSuccess) return e;
-  return launch_advance_step(reinterpret_cast<uint32_t*>(b->buf + b->B.step_off), s);
+// Enqueues the step at time t, whose Philox step count is the device counter
+// plus `offset`, with its statistics when t is a sampled step.
+hipError_t enqueue_step(rflbm_batch* b, int64_t t, uint32_t offset, hipStream_t s) {
+  const BatchArgs a = batch_args(b, offset);
+  const bool stats = stats_step(b, t);
+  hipError_t e = launch_batch_step(b->p[0].storage, (t & 1) != 0, b->rounds, b->all_ghost_eq, stats, a,
+                                   batch_grid(b), b->tile, s);
+  if (e == hipSuccess && stats) e = launch_batch_stats_reduce(a, static_cast<uint32_t>(b->n), b->tile, s);
+  return e;
 }
 
-// Captures graph_steps steps starting at an even parity into b->exec.
-rflbm_status build_graph(rflbm_batch* b) {
+// Captures graph_steps steps starting at an even step count t0 into b->exec:
+// step k reads the device counter plus k, and one last node advances the
+// counter by graph_steps, so a replay needs the counter at t mod 2^32.  Which
+// steps take statistics depends on t0 mod stats_every (kept in exec_phase).
+rflbm_status build_graph(rflbm_batch* b, int64_t t0) {
   drop_graph(b);
   hipStream_t cap = nullptr;
   RFLBM_HIP(hipStreamCreate(&cap));
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  for (int32_t k = 0; e == hipSuccess && k < b->graph_steps; ++k) e = enqueue_step(b, (k & 1) != 0, cap);
+  for (int32_t k = 0; e == hipSuccess && k < b->graph_steps; ++k)
+    e = enqueue_step(b, t0 + k, static_cast<uint32_t>(k), cap);
+  if (e == hipSuccess) e = launch_advance_step(step_counter(b), static_cast<uint32_t>(b->graph_steps), cap);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(cap, &g);
   if (e == hipSuccess) e = e2;
@@ -185,6 +207,7 @@ rflbm_status build_graph(rflbm_batch* b) {
   }
   b->graph = g;
   b->exec_steps = b->graph_steps;
+  b->exec_phase = b->stats_every > 0 ? t0 % b->stats_every : 0;
   return RFLBM_OK;
 }
 
@@ -196,16 +219,28 @@ rflbm_status do_batch_steps(rflbm_batch* b, int64_t nsteps) {
   rflbm_status st = RFLBM_OK;
   while (left > 0 && st == RFLBM_OK) {
     if (b->graph_steps > 0 && (b->t & 1) == 0 && left >= b->graph_steps) {
-      if (b->exec_steps != b->graph_steps) st = build_graph(b);
+      const int64_t phase = b->stats_every > 0 ? b->t % b->stats_every : 0;
+      if (b->exec_steps != b->graph_steps || b->exec_phase != phase) st = build_graph(b, b->t);
       if (st != RFLBM_OK) break;
+      const uint32_t t32 = static_cast<uint32_t>(b->t & 0xffffffffu);
+      if (b->dev_step != t32) {
+        if (const hipError_t e = launch_set_u32(step_counter(b), t32, b->stream); e != hipSuccess) {
+          st = hip_fail(RFLBM_EHIP, "step counter", e);
+          break;
+        }
+        b->dev_step = t32;
+      }
       if (const hipError_t e = hipGraphLaunch(b->exec, b->stream); e != hipSuccess) {
         st = hip_fail(RFLBM_EHIP, "hipGraphLaunch", e);
         break;
       }
+      b->dev_step += static_cast<uint32_t>(b->graph_steps);
       b->t += b->graph_steps;
       left -= b->graph_steps;
     } else {
-      if (const hipError_t e = enqueue_step(b, (b->t & 1) != 0, b->stream); e != hipSuccess) {
+      // outside a graph the step count goes in as the offset from the counter
+      const uint32_t offset = static_cast<uint32_t>(b->t & 0xffffffffu) - b->dev_step;
+      if (const hipError_t e = enqueue_step(b, b->t, offset, b->stream); e != hipSuccess) {
         st = hip_fail(RFLBM_EHIP, "batch step", e);
         break;
       }
@@ -371,11 +406,9 @@ rflbm_status rflbm_batch_step_separate(rflbm_batch* b, int64_t nsteps) {
   if (nsteps < 0) return fail(RFLBM_EINVAL, "nsteps must be >= 0");
   for (rflbm_lattice* v : b->views)
     if (v->t != b->t) return fail(RFLBM_ESTATE, "a replica was stepped or re-timed on its own");
-  uint32_t* step = reinterpret_cast<uint32_t*>(b->buf + b->B.step_off);
   for (int64_t k = 0; k < nsteps; ++k) {
     for (rflbm_lattice* v : b->views)
       if (rflbm_status s = lattice_steps(v, 1)) return s;
-    RFLBM_HIP(launch_advance_step(step, b->stream));
     b->t += 1;
   }
   return RFLBM_OK;
@@ -384,11 +417,31 @@ rflbm_status rflbm_batch_step_separate(rflbm_batch* b, int64_t nsteps) {
 rflbm_status rflbm_batch_set_step_count(rflbm_batch* b, int64_t t) {
   if (rflbm_status s = check_batch(b)) return s;
   if (t < 0) return fail(RFLBM_EINVAL, "step count must be >= 0");
+  // one scratch plane for the largest replica, taken before any replica moves,
+  // so that running out of memory leaves the whole batch unchanged
+  void* tmp = nullptr;
+  if ((t & 1) != (b->t & 1)) {
+    size_t bytes = 0;
+    for (rflbm_lattice* v : b->views) bytes = std::max(bytes, parity_scratch_bytes(v));
+    if (const hipError_t m = hipMalloc(&tmp, bytes); m != hipSuccess)
+      return hip_fail(RFLBM_ENOMEM, "re-layout scratch", m);
+  }
+  rflbm_status st = RFLBM_OK;
   for (rflbm_lattice* v : b->views)
-    if (rflbm_status s = lattice_set_step_count(v, t)) return s;
-  RFLBM_HIP(launch_set_u32(reinterpret_cast<uint32_t*>(b->buf + b->B.step_off),
-                           static_cast<uint32_t>(t & 0xffffffffu), b->stream));
+    if ((st = lattice_set_step_count_with(v, t, tmp)) != RFLBM_OK) break;
+  if (tmp) (void)hipFree(tmp);
+  if (st != RFLBM_OK) return st;
   b->t = t;
+  return RFLBM_OK;
+}
+
+rflbm_status rflbm_batch_stats_config(rflbm_batch* b, int32_t every) {
+  if (rflbm_status s = check_batch(b)) return s;
+  if (every < 0) return fail(RFLBM_EINVAL, "every must be >= 0");
+  b->stats_every = every;
+  // rflbm_batch_step_separate steps the views as single lattices
+  for (rflbm_lattice* v : b->views) v->stats_every = every;
+  drop_graph(b);
   return RFLBM_OK;
 }
 
@@ -457,21 +510,53 @@ rflbm_status rflbm_batch_autotune(rflbm_batch* b, int32_t trial_steps, const cha
         return rflbm_batch_set_launch(b, tile, bpc, b->graph_steps);
     }
   }
-  const int32_t keep_graph = b->graph_steps;
+  // the trials step a saved copy's original: every replica region (populations,
+  // flags, accumulators) is copied aside first and put back afterwards, with
+  // the step count, so a tuned batch continues exactly as an untuned one
+  const size_t state_bytes = b->B.reps_off;
+  void* saved = nullptr;
+  if (const hipError_t m = hipMalloc(&saved, state_bytes); m != hipSuccess)
+    return hip_fail(RFLBM_ENOMEM, "autotune state copy", m);
+  hipError_t ce = hipMemcpyAsync(saved, b->buf, state_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (ce == hipSuccess) ce = hipStreamSynchronize(b->stream);
+  if (ce != hipSuccess) {
+    (void)hipFree(saved);
+    return hip_fail(RFLBM_EHIP, "autotune state copy", ce);
+  }
+  const int64_t t0 = b->t;
+  const int32_t keep_graph = b->graph_steps, keep_tile = static_cast<int32_t>(b->tile), keep_bpc = b->bpc;
+  const int32_t keep_stats = b->stats_every;
+  (void)rflbm_batch_stats_config(b, 0);  // trials time plain steps
   double best = 1e300;
-  int32_t best_tile = 256, best_bpc = 0;
-  for (uint32_t tile : kTileChoices)
+  int32_t best_tile = keep_tile, best_bpc = keep_bpc;
+  rflbm_status st = RFLBM_OK;
+  for (uint32_t tile : kTileChoices) {
     for (int32_t bpc : kBpcChoices) {
-      if (rflbm_status s = rflbm_batch_set_launch(b, static_cast<int32_t>(tile), bpc, 0)) return s;
+      if ((st = rflbm_batch_set_launch(b, static_cast<int32_t>(tile), bpc, 0)) != RFLBM_OK) break;
       double ms = 0.0;
-      if (rflbm_status s = time_batch(b, 2, &ms)) return s;  // warm-up
-      if (rflbm_status s = time_batch(b, trial_steps, &ms)) return s;
+      if ((st = time_batch(b, 2, &ms)) != RFLBM_OK) break;  // warm-up
+      if ((st = time_batch(b, trial_steps, &ms)) != RFLBM_OK) break;
       if (ms < best) {
         best = ms;
         best_tile = static_cast<int32_t>(tile);
         best_bpc = bpc;
       }
     }
+    if (st != RFLBM_OK) break;
+  }
+  // restore the state and step count (every trial ran an even number of steps,
+  // so the stored layout has the parity of t0)
+  ce = hipMemcpyAsync(b->buf, saved, state_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (ce == hipSuccess) ce = hipStreamSynchronize(b->stream);
+  (void)hipFree(saved);
+  b->t = t0;
+  for (rflbm_lattice* v : b->views) v->t = t0;
+  (void)rflbm_batch_stats_config(b, keep_stats);
+  if (ce != hipSuccess) return hip_fail(RFLBM_EHIP, "autotune state restore", ce);
+  if (st != RFLBM_OK) {
+    (void)rflbm_batch_set_launch(b, keep_tile, keep_bpc, keep_graph);
+    return st;
+  }
   if (rflbm_status s = rflbm_batch_set_launch(b, best_tile, best_bpc, keep_graph)) return s;
   if (cache_path) {
     std::ofstream outf(cache_path, std::ios::app);

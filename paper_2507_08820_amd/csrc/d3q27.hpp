@@ -73,16 +73,39 @@ __host__ __device__ __forceinline__ void inv3(float& lo, float& mid, float& hi) 
   mid = fmaf(2.0f / 3.0f, m0, -m2);
 }
 
-// In-place forward transform of the 27 registers: populations -> moments.
-__host__ __device__ __forceinline__ void forward27(float v[kQ]) {
-#pragma unroll
-  for (int g = 0; g < 9; ++g) fwd3(v[3 * g], v[3 * g + 1], v[3 * g + 2]);  // x
+// Scaled inverse.  With the degree-p input of a 3-point inverse pre-multiplied by
+// s(p), s = (2/3, 1/2, 1/2), the transform takes four operations:
+// f0 = m0' - 2 m2', f+- = m0' / 4 + m2' +- m1'.  Pre-multiplying mode
+// (px, py, pz) by inv_scale = s(px) s(py) s(pz) lets all three sweeps use it,
+// since each sweep is linear and leaves the other axes' factors in place.
+constexpr double inv_axis_scale(int p) { return p == 0 ? 2.0 / 3.0 : 0.5; }
+constexpr double inv_scale(int slot) {
+  return inv_axis_scale(slot % 3) * inv_axis_scale((slot / 3) % 3) * inv_axis_scale(slot / 9);
+}
+
+__host__ __device__ __forceinline__ void inv3_scaled(float& lo, float& mid, float& hi) {
+  const float m0 = lo, m1 = mid, m2 = hi;
+  const float t = fmaf(0.25f, m0, m2);
+  lo = t - m1;
+  hi = t + m1;
+  mid = fmaf(-2.0f, m2, m0);
+}
+
+// The y and z sweeps of the forward transform (after the x sweep).
+__host__ __device__ __forceinline__ void forward27_yz(float v[kQ]) {
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
     for (int ix = 0; ix < 3; ++ix) fwd3(v[ix + 9 * iz], v[ix + 3 + 9 * iz], v[ix + 6 + 9 * iz]);  // y
 #pragma unroll
   for (int g = 0; g < 9; ++g) fwd3(v[g], v[g + 9], v[g + 18]);  // z
+}
+
+// In-place forward transform of the 27 registers: populations -> moments.
+__host__ __device__ __forceinline__ void forward27(float v[kQ]) {
+#pragma unroll
+  for (int g = 0; g < 9; ++g) fwd3(v[3 * g], v[3 * g + 1], v[3 * g + 2]);  // x
+  forward27_yz(v);
 }
 
 // In-place inverse transform: moments -> populations.
@@ -95,6 +118,19 @@ __host__ __device__ __forceinline__ void inverse27(float v[kQ]) {
     for (int ix = 0; ix < 3; ++ix) inv3(v[ix + 9 * iz], v[ix + 3 + 9 * iz], v[ix + 6 + 9 * iz]);  // y
 #pragma unroll
   for (int g = 0; g < 9; ++g) inv3(v[3 * g], v[3 * g + 1], v[3 * g + 2]);  // x
+}
+
+// In-place inverse of pre-scaled moments (slot s holding inv_scale(s) m):
+// moments -> populations, the same result as inverse27 on unscaled moments.
+__host__ __device__ __forceinline__ void inverse27_scaled(float v[kQ]) {
+#pragma unroll
+  for (int g = 0; g < 9; ++g) inv3_scaled(v[g], v[g + 9], v[g + 18]);  // z
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz)
+#pragma unroll
+    for (int ix = 0; ix < 3; ++ix) inv3_scaled(v[ix + 9 * iz], v[ix + 3 + 9 * iz], v[ix + 6 + 9 * iz]);  // y
+#pragma unroll
+  for (int g = 0; g < 9; ++g) inv3_scaled(v[3 * g], v[3 * g + 1], v[3 * g + 2]);  // x
 }
 
 }  // namespace rflbm

@@ -46,6 +46,8 @@ struct StepArgs {
   float rho0;
   float lam_s;           // 1 - omega_s (deviatoric second-order modes)
   float lam_b_minus_s;   // (1 - omega_b) - (1 - omega_s) (trace of the xx, yy, zz block)
+  // noise amplitudes, each multiplied by inv_scale of its mode's register slot
+  // (d3q27.hpp), the scale the step kernels carry the modes in
   float amp_s;           // sqrt(kT b_4 / cs2) s(omega_s), s(w) = sqrt(w (2 - w)); modes 4..6
   float amp_b_minus_s;   // sqrt(kT b_4 / cs2) (s(omega_b) - s(omega_s))
   float amp_off;         // sqrt(kT b_7 / cs2) s(omega_s), modes 7..9
@@ -68,23 +70,30 @@ struct ReplicaArgs {
   uint32_t nodes;    // nx * ny * nz
   FastDiv div_x;     // division by nx
   FastDiv div_xy;    // division by nx * ny
+  double* acc;       // the replica's statistics accumulators (kAccDoubles)
 };
 
 struct BatchArgs {
   const ReplicaArgs* __restrict__ reps;  // device table, one entry per replica
   const uint32_t* __restrict__ tile_rep; // replica of each tile
   uint32_t ntiles;                       // tiles of blockDim.x consecutive nodes, all replicas
-  const uint32_t* step;                  // device step counter (t mod 2^32)
+  const uint32_t* step;                  // device step counter
+  uint32_t step_offset;                  // t mod 2^32 = *step + step_offset
+  uint32_t partial_pitch;                // doubles between partial columns (>= ntiles)
+  double* partials;                      // statistics partials [kNumStats][partial_pitch]
 };
 
 // One step of every replica (persistent grid of `grid` blocks walking the tiles);
-// the Philox step counter is read from b.step on the device, the parity `odd`
-// must match it.  all_ghost_eq: every replica has every omega_g = 1 (then the
-// kernel variant without the general ghost relaxation runs).
-hipError_t launch_batch_step(int storage, bool odd, int rounds, bool all_ghost_eq, const BatchArgs& b,
-                             uint32_t grid, uint32_t tile, hipStream_t stream);
-// *step += 1 on the device (a graph node after each captured batch step).
-hipError_t launch_advance_step(uint32_t* step, hipStream_t stream);
+// the Philox step count is *b.step + b.step_offset, and the parity `odd` must
+// match it.  all_ghost_eq: every replica has every omega_g = 1 (then the
+// kernel variant without the general ghost relaxation runs).  stats: each
+// tile's statistics go to column `tile` of b.partials.
+hipError_t launch_batch_step(int storage, bool odd, int rounds, bool all_ghost_eq, bool stats,
+                             const BatchArgs& b, uint32_t grid, uint32_t tile, hipStream_t stream);
+// Adds each replica's tile partials (tiles of `tile` nodes) into its accumulators.
+hipError_t launch_batch_stats_reduce(const BatchArgs& b, uint32_t nrep, uint32_t tile, hipStream_t stream);
+// *step += delta on the device (the last node of a captured graph of steps).
+hipError_t launch_advance_step(uint32_t* step, uint32_t delta, hipStream_t stream);
 
 // Launch configuration of the step kernel.
 struct Launch {
@@ -104,9 +113,12 @@ hipError_t launch_step_wave(int storage, int rounds, const StepArgs& a, hipStrea
 // True when the odd step can run in whole-row blocks: nx a multiple of 64, at
 // most 64 kMaxRowWaves.
 bool row_kernel_fits(uint32_t nx);
-// Odd step without statistics, one block per x-row (a.xcd_remap applies to
-// rows); every store is a whole aligned cache line.
-hipError_t launch_step_row(int storage, int rounds, const StepArgs& a, hipStream_t stream);
+// Odd step, one block per x-row (a.xcd_remap applies to rows); every store is
+// a whole aligned cache line.  With stats, one statistics partial per block of
+// the row_grid(ny, nz) blocks.
+hipError_t launch_step_row(int storage, int rounds, bool stats, const StepArgs& a, hipStream_t stream);
+// Number of blocks of the whole-row odd step: ny nz rounded up to a multiple of 8.
+uint32_t row_grid(uint32_t ny, uint32_t nz);
 
 // Deterministic reduction of the statistics partials into the accumulators.
 // scratch holds at least 2 * kNumStats * ceil(grid / 2048) doubles.

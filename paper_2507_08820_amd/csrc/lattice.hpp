@@ -95,6 +95,11 @@ void lattice_release(rflbm_lattice* L);
 rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps);
 rflbm_status lattice_set_params(rflbm_lattice* L, const rflbm_params* p);
 rflbm_status lattice_set_step_count(rflbm_lattice* L, int64_t t);
+// Bytes of scratch a change of parity of L needs (one population plane).
+size_t parity_scratch_bytes(const rflbm_lattice* L);
+// lattice_set_step_count with the caller's scratch (at least
+// parity_scratch_bytes(L) bytes of device memory; unused if the parity stays).
+rflbm_status lattice_set_step_count_with(rflbm_lattice* L, int64_t t, void* tmp);
 
 }  // namespace rflbm
 

@@ -65,14 +65,22 @@ __device__ __forceinline__ float word_to_uniform(uint32_t w) {
   return fmaf(static_cast<float>(w >> 8), 0x1p-24f, 0x1p-24f);
 }
 
-// Box-Muller pair from two words (radius word, angle word).
-__device__ __forceinline__ void box_muller(uint32_t wr, uint32_t wa, float& z0, float& z1) {
+constexpr float kMinus2Ln2 = -1.38629436111989061883f;  // -2 ln 2
+
+// Box-Muller pair from two words (radius word, angle word), both normals
+// multiplied by sqrt(c / (-2 ln 2)): the radius is sqrt(c log2 U0), so c = -2 ln 2
+// gives standard normals and c = -2 ln 2 rho gives sqrt(rho) times them.
+__device__ __forceinline__ void box_muller_scaled(uint32_t wr, uint32_t wa, float c, float& z0, float& z1) {
   const float ur = word_to_uniform(wr);
   const float ua = word_to_uniform(wa);
-  constexpr float kMinus2Ln2 = -1.38629436111989061883f;  // -2 ln 2
-  const float rad = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(ur));
+  const float rad = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(ur));
   z0 = rad * __builtin_amdgcn_cosf(ua);
   z1 = rad * __builtin_amdgcn_sinf(ua);
+}
+
+// Standard normal Box-Muller pair.
+__device__ __forceinline__ void box_muller(uint32_t wr, uint32_t wa, float& z0, float& z1) {
+  box_muller_scaled(wr, wa, kMinus2Ln2, z0, z1);
 }
 
 }  // namespace rflbm

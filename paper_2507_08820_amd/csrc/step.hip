@@ -144,6 +144,14 @@ __device__ __forceinline__ uint32_t wave_shift_left(uint32_t v) {
   return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), kDppWaveShl1, 0xf, 0xf, false));
 }
 
+// Sum over the 64 lanes of a wave in a fixed order (xor butterfly); every lane
+// gets the same bits.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // Whole-row blocks (blockDim.x = nx, so lane = x mod 64): replaces v[i], for
 // every population with c_x = +-1, by the word that lane x - c_x holds.
 // Inside a wave that is a shift by one lane; the one word per wave and
@@ -199,6 +207,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 
   if (active) {
     const uint32_t step = a.step;
+    constexpr bool STATS_WAVE = false;
+    [[maybe_unused]] float (*stat_wave)[kMaxRowWaves] = nullptr;
     constexpr bool SMALL_BOX = false;
     constexpr bool BUFFER_ACCESS = true;
     constexpr bool ROW_SHIFT = false;
@@ -237,8 +247,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 template <int S, int ROUNDS, bool GEQ>
 __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
   constexpr bool ODD = false, STATS = false, SMALL_BOX = false, ROW_SHIFT = false, BUFFER_ACCESS = true;
-  constexpr bool GHOST_EQ = GEQ;
+  constexpr bool GHOST_EQ = GEQ, STATS_WAVE = false;
   [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
+  [[maybe_unused]] float (*stat_wave)[kMaxRowWaves] = nullptr;
   [[maybe_unused]] const uint32_t tid = 0;
   [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
   [[maybe_unused]] uint32_t (*row_edge_out)[kMaxRowWaves] = nullptr;
@@ -257,18 +268,26 @@ __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
 // Odd step of one box in whole-row blocks: block b covers the x-row (y, z) of
 // row index y + ny z (blockDim.x = nx, a multiple of 64 up to 1024), so that
 // the +-1 shifts in x stay inside the block and every load and store is a
-// whole aligned cache line (see row_shift).  Without statistics.
-template <int S, int ROUNDS, bool GEQ>
+// whole aligned cache line (see row_shift).  With STATS, each wave sums its
+// nodes' statistics, and the block adds its waves' sums in FP64 (fixed order)
+// into one partial per block, as step_kernel does.
+template <int S, int ROUNDS, bool GEQ, bool STATS>
 __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepArgs a) {
-  constexpr bool ODD = true, STATS = false, SMALL_BOX = false, ROW_SHIFT = true, BUFFER_ACCESS = true;
-  constexpr bool GHOST_EQ = GEQ;
+  constexpr bool ODD = true, SMALL_BOX = false, ROW_SHIFT = true, BUFFER_ACCESS = true;
+  constexpr bool GHOST_EQ = GEQ, STATS_WAVE = true;
   [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
   [[maybe_unused]] const uint32_t tid = 0;
   __shared__ uint32_t row_edge_in[18][kMaxRowWaves];   // gather (stored words)
   __shared__ uint32_t row_edge_out[18][kMaxRowWaves];  // scatter (FP32 values)
+  __shared__ float stat_wave[STATS ? kNumStats : 1][kMaxRowWaves];
   uint32_t row = blockIdx.x;
   if (a.xcd_remap) row = (row & 7u) * (gridDim.x >> 3) + (row >> 3);
-  if (row >= a.ny * a.nz) return;  // the whole block: rounding of the grid to 8
+  if (row >= a.ny * a.nz) {  // the whole block: rounding of the grid to 8
+    if constexpr (STATS) {
+      if (threadIdx.x < kNumStats) a.partials[static_cast<size_t>(threadIdx.x) * gridDim.x + blockIdx.x] = 0.0;
+    }
+    return;
+  }
   const uint32_t x = threadIdx.x;
 #if RFLBM_ROW_GROUP_Y * RFLBM_ROW_GROUP_Z > 1
   // rows visited in groups of GY x GZ (y, z) so that the 9 row blocks a row
@@ -292,18 +311,29 @@ __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepA
 #endif
   const uint32_t step = a.step;
 #include "node_body.inc"
+  if constexpr (STATS) {
+    __syncthreads();
+    if (x < kNumStats) {
+      double acc = 0.0;
+      for (uint32_t w = 0; w < (a.nx >> 6); ++w) acc += static_cast<double>(stat_wave[x][w]);
+      a.partials[static_cast<size_t>(x) * gridDim.x + blockIdx.x] = acc;
+    }
+  }
 }
 
 // Many boxes: tile t holds blockDim.x consecutive nodes (flattened index) of
 // replica tile_rep[t]; a persistent grid walks the tiles.  The step count (the
-// Philox counter) comes from device memory so that a captured graph of several
-// steps can be replayed; the parity is a template parameter, and the host only
-// replays graphs of an even number of steps from an even step count.  GEQ:
-// every replica has every omega_g = 1; otherwise each replica's own setting
-// is read at run time.
-template <int S, bool ODD, int ROUNDS, bool GEQ>
+// Philox counter) is the device counter plus b.step_offset, so that a captured
+// graph of several steps (offsets 0, 1, ...) can be replayed from any t; the
+// parity is a template parameter, and the host only replays graphs of an even
+// number of steps from an even step count.  GEQ: every replica has every
+// omega_g = 1; otherwise each replica's own setting is read at run time.
+// STATS: each tile's statistics are reduced in the block (fixed order, FP64)
+// into column t of b.partials, for batch_stats_reduce.
+template <int S, bool ODD, int ROUNDS, bool GEQ, bool STATS>
 __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
-  constexpr bool STATS = false;
+  constexpr bool STATS_WAVE = false;
+  [[maybe_unused]] float (*stat_wave)[kMaxRowWaves] = nullptr;
   constexpr bool SMALL_BOX = true;  // every replica region is below 4 GiB
   // buffer instructions measured faster for 16-bit storage, global ones for
   // FP32 (64 replicas of 32^3..96^3: 38.9 vs 36.6 and 24.6 vs 25.9 GLUPS)
@@ -311,15 +341,16 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
   constexpr bool ROW_SHIFT = false;
   [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
   [[maybe_unused]] uint32_t (*row_edge_out)[kMaxRowWaves] = nullptr;
-  float (*stat_lds)[kBlock] = nullptr;
-  const uint32_t tid = 0;
+  __shared__ float stat_lds[STATS ? kNumStats : 1][kBlock];
+  __shared__ double stat_part[STATS ? kNumStats : 1][kBlock / 32];
+  const uint32_t tid = threadIdx.x;
   // the tables are read-only for the whole launch: constant address space,
   // so the per-tile lookups are scalar loads
   typedef __attribute__((address_space(4))) const ReplicaArgs CReps;
   typedef __attribute__((address_space(4))) const uint32_t CU32;
   CReps* const reps = (CReps*)(b.reps);
   CU32* const tile_rep = (CU32*)(b.tile_rep);
-  const uint32_t step = *(CU32*)(b.step);
+  const uint32_t step = *(CU32*)(b.step) + b.step_offset;
   for (uint32_t tile = blockIdx.x; tile < b.ntiles; tile += gridDim.x) {
     CReps& r = reps[tile_rep[tile]];
     __attribute__((address_space(4))) const StepArgs& a = r.a;
@@ -331,14 +362,61 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
       const uint32_t x = rem - y * a.nx;
       const bool GHOST_EQ = GEQ || a.ghost_eq != 0u;
 #include "node_body.inc"
+    } else if constexpr (STATS) {
+#pragma unroll
+      for (int c = 0; c < kNumStats; ++c) stat_lds[c][tid] = 0.0f;
+    }
+    if constexpr (STATS) {
+      // parts of 32 nodes per column, then the parts in order, in FP64
+      const uint32_t parts = blockDim.x / 32;
+      __syncthreads();
+      if (tid < kNumStats * parts) {
+        const uint32_t c = tid / parts, p = tid - c * parts;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int e = 0; e < 32; ++e) acc += static_cast<double>(stat_lds[c][p * 32 + e]);
+        stat_part[c][p] = acc;
+      }
+      __syncthreads();
+      if (tid < kNumStats) {
+        double acc = 0.0;
+        for (uint32_t p = 0; p < parts; ++p) acc += stat_part[tid][p];
+        b.partials[static_cast<size_t>(tid) * b.partial_pitch + tile] = acc;
+      }
+      __syncthreads();  // stat_lds is refilled by the block's next tile
     }
   }
-  (void)stat_lds;
-  (void)tid;
 }
 
-__global__ void advance_step(uint32_t* step) {
-  if (threadIdx.x == 0) *step += 1u;
+// Statistics of a batch step: block r adds the tile partials of replica r in
+// tile order (8 strided parts per column, then the parts in order, FP64) and
+// accumulates them into the replica's accumulators like accumulate_stats.
+__global__ void __launch_bounds__(256) batch_stats_reduce(const BatchArgs b, uint32_t tile_nodes) {
+  const ReplicaArgs& r = b.reps[blockIdx.x];
+  const uint32_t ntiles = (r.nodes + tile_nodes - 1) / tile_nodes;
+  __shared__ double part[kNumStats][8];
+  const uint32_t tid = threadIdx.x;
+  if (tid < kNumStats * 8) {
+    const uint32_t c = tid >> 3, p = tid & 7;
+    const double* col = b.partials + static_cast<size_t>(c) * b.partial_pitch + r.tile0;
+    double acc = 0.0;
+    for (uint32_t k = p; k < ntiles; k += 8) acc += col[k];
+    part[c][p] = acc;
+  }
+  __syncthreads();
+  if (tid < kNumStats) {
+    double sum = 0.0;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) sum += part[tid][p];
+    r.acc[tid] += sum;
+    if (tid == 0) r.acc[kNumStats] += 1.0;
+    if (tid == 0) r.acc[kNumStats + 1] = sum;                          // mass deviation
+    if (tid >= 2 && tid <= 4) r.acc[kNumStats + tid] = sum;            // momentum
+  }
+}
+
+__global__ void advance_step(uint32_t* step, uint32_t delta) {
+  if (threadIdx.x == 0) *step += delta;
 }
 
 // Sums 2048 consecutive entries of one column per block (fixed order).
@@ -386,10 +464,10 @@ hipError_t launch_t(const StepArgs& a, const Launch& l, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int S, int R>
+template <int S, int R, bool ST>
 void launch_row_g(const StepArgs& a, dim3 g, dim3 blk, hipStream_t s) {
-  if (a.ghost_eq) hipLaunchKernelGGL((step_row_kernel<S, R, true>), g, blk, 0, s, a);
-  else hipLaunchKernelGGL((step_row_kernel<S, R, false>), g, blk, 0, s, a);
+  if (a.ghost_eq) hipLaunchKernelGGL((step_row_kernel<S, R, true, ST>), g, blk, 0, s, a);
+  else hipLaunchKernelGGL((step_row_kernel<S, R, false, ST>), g, blk, 0, s, a);
 }
 
 template <int S, int R>
@@ -415,13 +493,13 @@ hipError_t launch_s(bool odd, int rounds, bool stats, const StepArgs& a, const L
   return stats ? launch_r<S, false, true>(rounds, a, l, s) : launch_r<S, false, false>(rounds, a, l, s);
 }
 
-template <int S>
+template <int S, bool ST>
 hipError_t launch_row_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_t s) {
   const dim3 g(grid), blk(a.nx);
   switch (rounds) {
-    case 0: launch_row_g<S, 0>(a, g, blk, s); break;
-    case 7: launch_row_g<S, 7>(a, g, blk, s); break;
-    case 10: launch_row_g<S, 10>(a, g, blk, s); break;
+    case 0: launch_row_g<S, 0, ST>(a, g, blk, s); break;
+    case 7: launch_row_g<S, 7, ST>(a, g, blk, s); break;
+    case 10: launch_row_g<S, 10, ST>(a, g, blk, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -455,15 +533,23 @@ hipError_t launch_step_wave(int storage, int rounds, const StepArgs& a, hipStrea
 
 bool row_kernel_fits(uint32_t nx) { return nx % 64 == 0 && nx >= 64 && nx <= kMaxRowWaves * 64; }
 
-hipError_t launch_step_row(int storage, int rounds, const StepArgs& a, hipStream_t stream) {
+uint32_t row_grid(uint32_t ny, uint32_t nz) {
+  const uint64_t rows = static_cast<uint64_t>(ny) * nz;
+  return static_cast<uint32_t>((rows + 7) / 8 * 8);
+}
+
+hipError_t launch_step_row(int storage, int rounds, bool stats, const StepArgs& a, hipStream_t stream) {
   if (!row_kernel_fits(a.nx)) return hipErrorInvalidConfiguration;
   const uint64_t rows = static_cast<uint64_t>(a.ny) * a.nz;
   if (rows >= (1ull << 31)) return hipErrorInvalidConfiguration;
-  const uint32_t grid = static_cast<uint32_t>((rows + 7) / 8 * 8);
+  const uint32_t grid = row_grid(a.ny, a.nz);
   switch (storage) {
-    case kF32: return launch_row_s<kF32>(rounds, a, grid, stream);
-    case kF16: return launch_row_s<kF16>(rounds, a, grid, stream);
-    case kBF16: return launch_row_s<kBF16>(rounds, a, grid, stream);
+    case kF32: return stats ? launch_row_s<kF32, true>(rounds, a, grid, stream)
+                            : launch_row_s<kF32, false>(rounds, a, grid, stream);
+    case kF16: return stats ? launch_row_s<kF16, true>(rounds, a, grid, stream)
+                            : launch_row_s<kF16, false>(rounds, a, grid, stream);
+    case kBF16: return stats ? launch_row_s<kBF16, true>(rounds, a, grid, stream)
+                             : launch_row_s<kBF16, false>(rounds, a, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -488,15 +574,22 @@ hipError_t launch_step(int storage, bool odd, int rounds, bool stats, const Step
   }
 }
 
-hipError_t launch_batch_step(int storage, bool odd, int rounds, bool all_ghost_eq, const BatchArgs& b,
-                             uint32_t grid, uint32_t tile, hipStream_t stream) {
+hipError_t launch_batch_step(int storage, bool odd, int rounds, bool all_ghost_eq, bool stats,
+                             const BatchArgs& b, uint32_t grid, uint32_t tile, hipStream_t stream) {
   if (tile != 128 && tile != 256) return hipErrorInvalidConfiguration;
+  if (stats && !b.partials) return hipErrorInvalidValue;
   const dim3 g(grid), blk(tile);
-#define RFLBM_BATCH_G(S, O, R)                                                                 \
-  if (all_ghost_eq)                                                                            \
-    hipLaunchKernelGGL((batch_kernel<S, O, R, true>), g, blk, 0, stream, b);                   \
+#define RFLBM_BATCH_ST(S, O, R, G)                                                             \
+  if (stats)                                                                                   \
+    hipLaunchKernelGGL((batch_kernel<S, O, R, G, true>), g, blk, 0, stream, b);                \
   else                                                                                         \
-    hipLaunchKernelGGL((batch_kernel<S, O, R, false>), g, blk, 0, stream, b);
+    hipLaunchKernelGGL((batch_kernel<S, O, R, G, false>), g, blk, 0, stream, b);
+#define RFLBM_BATCH_G(S, O, R)                                                                 \
+  if (all_ghost_eq) {                                                                          \
+    RFLBM_BATCH_ST(S, O, R, true)                                                              \
+  } else {                                                                                     \
+    RFLBM_BATCH_ST(S, O, R, false)                                                             \
+  }
 #define RFLBM_BATCH_R(S, O)                                                                    \
   switch (rounds) {                                                                            \
     case 0: RFLBM_BATCH_G(S, O, 0) break;                                                      \
@@ -519,11 +612,18 @@ hipError_t launch_batch_step(int storage, bool odd, int rounds, bool all_ghost_e
 #undef RFLBM_BATCH
 #undef RFLBM_BATCH_R
 #undef RFLBM_BATCH_G
+#undef RFLBM_BATCH_ST
   return hipGetLastError();
 }
 
-hipError_t launch_advance_step(uint32_t* step, hipStream_t stream) {
-  hipLaunchKernelGGL(advance_step, dim3(1), dim3(64), 0, stream, step);
+hipError_t launch_batch_stats_reduce(const BatchArgs& b, uint32_t nrep, uint32_t tile, hipStream_t stream) {
+  if (nrep == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_stats_reduce, dim3(nrep), dim3(256), 0, stream, b, tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_step(uint32_t* step, uint32_t delta, hipStream_t stream) {
+  hipLaunchKernelGGL(advance_step, dim3(1), dim3(64), 0, stream, step, delta);
   return hipGetLastError();
 }
 

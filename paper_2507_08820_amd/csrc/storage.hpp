@@ -16,10 +16,15 @@ namespace rflbm {
 template <int S>
 struct Codec;
 
+// decode(q, sigma) = q sigma; decode_add(q, sigma, c) = q sigma + c and
+// decode_sub(q, sigma, c) = c - q sigma, each one rounding (a fused
+// multiply-add, or an exact add where sigma is 1).
 template <>
 struct Codec<kF32> {
   using T = float;
   __device__ __forceinline__ static float decode(T q, float) { return q; }
+  __device__ __forceinline__ static float decode_add(T q, float, float c) { return q + c; }
+  __device__ __forceinline__ static float decode_sub(T q, float, float c) { return c - q; }
   __device__ __forceinline__ static T encode(float d, float) { return d; }
 };
 
@@ -29,6 +34,12 @@ struct Codec<kF16> {
   __device__ __forceinline__ static float decode(T q, float sigma) {
     return static_cast<float>(q) * sigma;
   }
+  __device__ __forceinline__ static float decode_add(T q, float sigma, float c) {
+    return fmaf(static_cast<float>(q), sigma, c);
+  }
+  __device__ __forceinline__ static float decode_sub(T q, float sigma, float c) {
+    return fmaf(static_cast<float>(q), -sigma, c);
+  }
   __device__ __forceinline__ static T encode(float d, float inv_sigma) {
     return static_cast<_Float16>(d * inv_sigma);
   }
@@ -37,9 +48,10 @@ struct Codec<kF16> {
 template <>
 struct Codec<kBF16> {
   using T = uint16_t;  // raw bfloat16 bits
-  __device__ __forceinline__ static float decode(T q, float sigma) {
-    return __uint_as_float(static_cast<uint32_t>(q) << 16) * sigma;
-  }
+  __device__ __forceinline__ static float widen(T q) { return __uint_as_float(static_cast<uint32_t>(q) << 16); }
+  __device__ __forceinline__ static float decode(T q, float sigma) { return widen(q) * sigma; }
+  __device__ __forceinline__ static float decode_add(T q, float sigma, float c) { return fmaf(widen(q), sigma, c); }
+  __device__ __forceinline__ static float decode_sub(T q, float sigma, float c) { return fmaf(widen(q), -sigma, c); }
   __device__ __forceinline__ static T encode(float d, float inv_sigma) {
     const uint32_t u = __float_as_uint(d * inv_sigma);
     // round to nearest even on the 16 dropped bits (finite inputs)

@@ -186,18 +186,25 @@ def test_params_round_trip_and_merge():
 
 
 def test_field_sizes_are_checked_before_the_library_reads_them():
-    """Density and velocity fields reach the library only with N and 3 N
-    values: a scalar density is broadcast, a box-shaped one flattened, a wrong
-    size raises before any call."""
+    """Density and velocity fields reach the library only as N and 3 N values
+    in node order: a scalar density is broadcast, a box-shaped one must be
+    indexed [z, y, x] (shape (nz, ny, nx)) and is flattened; any other shape,
+    including the transposed box, raises before any call."""
     import numpy as np
 
     torch = pytest.importorskip("torch")
+    dims = (4, 3, 2)
     n = 4 * 3 * 2
-    assert _binding._field(1.1, "cpu", n).shape == (n,)
-    assert _binding._field(np.ones((2, 3, 4)), "cpu", n).shape == (n,)
-    assert _binding._field(np.zeros((3, n)), "cpu", n, rows=3).shape == (3, n)
-    for bad, rows in ((np.ones(n + 1), 1), (torch.ones(n - 1), 1), (np.zeros((3, n - 1)), 3)):
+    assert _binding._field(1.1, "cpu", dims).shape == (n,)
+    box = np.arange(n, dtype=np.float64).reshape(2, 3, 4)  # [z, y, x]
+    got = _binding._field(box, "cpu", dims).numpy()
+    assert got.shape == (n,)
+    assert got[1 + 4 * (2 + 3 * 1)] == box[1, 2, 1]  # node n = x + nx (y + ny z) at (x, y, z) = (1, 2, 1)
+    assert _binding._field(np.zeros((3, n)), "cpu", dims, rows=3).shape == (3, n)
+    assert _binding._field(np.zeros((3, 2, 3, 4)), "cpu", dims, rows=3).shape == (3, n)
+    for bad, rows in ((np.ones(n + 1), 1), (torch.ones(n - 1), 1), (np.zeros((3, n - 1)), 3),
+                      (np.ones((4, 3, 2)), 1), (np.zeros((n, 3)), 3), (np.zeros((3, 4, 3, 2)), 3)):
         with pytest.raises(ValueError):
-            _binding._field(bad, "cpu", n, rows=rows)
+            _binding._field(bad, "cpu", dims, rows=rows)
     with pytest.raises(ValueError):
         _binding.copy(torch.empty(64, dtype=torch.uint8), torch.empty(32, dtype=torch.uint8), 64)

@@ -40,6 +40,18 @@ def start_state(ora, dims, seed):
     return f + 1e-3 * w * wl.normal_array(f.shape, seed + 7)
 
 
+def same_stats(a, b):
+    """Bit-for-bit equality of two statistics records."""
+    return a.keys() == b.keys() and all(np.array_equal(a[k], b[k]) for k in a)
+
+
+def close_stats(a, b):
+    """Equal sample counts, sums equal to FP64 rounding (another summation order)."""
+    assert a["samples"] == b["samples"] and a["nodes"] == b["nodes"]
+    for k in a:
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-11, atol=1e-15, err_msg=k)
+
+
 def make_batch(rf, ora, storage="f32", **launch):
     b = rf.Batch(REPLICAS, storage=storage)
     for r, rep in enumerate(REPLICAS):
@@ -134,19 +146,33 @@ def test_two_replicas_match_oracle(rf, ora):
 
 
 def test_autotune_and_cache(rf, ora, tmp_path):
+    """The autotuner's trial steps run on a saved copy of the state: afterwards
+    the batch is at the same step count with the same populations and
+    statistics, and continues bit for bit like an untuned batch."""
     cache = tmp_path / "tune.txt"
     b = make_batch(rf, ora)
-    lats = singles(rf, ora)
+    b.step(3)
+    b.stats_config(2)
+    b.step(2)
+    before = [b[r].populations() for r in range(len(REPLICAS))]
+    stats_before = [b[r].stats() for r in range(len(REPLICAS))]
+    untuned = make_batch(rf, ora)
+    untuned.step(3)
+    untuned.stats_config(2)
+    untuned.step(2)
     shape = b.autotune(trial_steps=4, cache_path=cache)
     assert shape[0] in (128, 256)
     assert cache.exists() and cache.read_text().strip()
-    t = b.t
-    for lat in lats:
-        lat.step(t)
-    b.step(4)
-    for r, lat in enumerate(lats):
-        lat.step(4)
-        assert bool((b[r].populations() == lat.populations()).all())
+    assert b.t == 5
+    for r in range(len(REPLICAS)):
+        assert bool((b[r].populations() == before[r]).all()), r
+        assert same_stats(b[r].stats(), stats_before[r]), r
+    b.step(7)
+    untuned.step(7)
+    for r in range(len(REPLICAS)):
+        assert bool((b[r].populations() == untuned[r].populations()).all()), r
+        # the tile size orders the FP64 partial sums: equal to rounding
+        close_stats(b[r].stats(), untuned[r].stats())
     b2 = make_batch(rf, ora)
     assert b2.autotune(trial_steps=4, cache_path=cache)[:2] == shape[:2]
     assert b2.t == 0  # a cached choice takes no trial steps
@@ -156,6 +182,9 @@ def test_views_refuse_own_stepping_and_checkpoint(rf, ora):
     b = make_batch(rf, ora, graph_steps=2)
     with pytest.raises(rf.RFLBMError) as e:
         b[0].step(1)
+    assert e.value.status == -5
+    with pytest.raises(rf.RFLBMError) as e:
+        b[0].stats_config(1)  # the statistics schedule belongs to the batch
     assert e.value.status == -5
     b.step(3)
     snap = [b[r].populations() for r in range(len(REPLICAS))]
@@ -182,3 +211,56 @@ def test_batch_replica_table_workload(rf):
     b.sync()
     m = b[5].moments(rf.M_RHO).double().cpu().numpy()
     assert abs(m.mean() - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("launch", [dict(tile=256, blocks_per_cu=0, graph_steps=0),
+                                    dict(tile=128, blocks_per_cu=4, graph_steps=6)])
+def test_batch_statistics_match_standalone_lattices(rf, ora, launch):
+    """Batch statistics (every 3rd step, sampled inside the batched step) equal
+    the stand-alone lattices' to FP64 rounding, sample counts exactly; a
+    graph length that is not a multiple of the sampling period re-captures
+    with the right phase."""
+    print(f"[gpu] batch statistics {launch}", flush=True)
+    b = make_batch(rf, ora, **launch)
+    lats = singles(rf, ora)
+    b.stats_config(3)
+    for lat in lats:
+        lat.stats_config(3)
+    b.step(1)
+    b.step(20)
+    for lat in lats:
+        lat.step(21)
+    for r, lat in enumerate(lats):
+        got, want = b[r].stats(), lat.stats()
+        assert got["samples"] == want["samples"] == 7, r
+        for key in ("sum_drho2", "sum_j2", "sum_u2", "sum_pi2"):
+            np.testing.assert_allclose(got[key], want[key], rtol=1e-9, atol=1e-300, err_msg=f"{r} {key}")
+        for key in ("sum_drho", "sum_j", "sum_pi", "mass_dev", "momentum"):
+            np.testing.assert_allclose(got[key], want[key], rtol=1e-9, atol=1e-9 * lat.n, err_msg=f"{r} {key}")
+        assert bool((b[r].populations() == lat.populations()).all()), r
+
+
+def test_batch_statistics_graph_equals_eager(rf, ora):
+    """The same statistics schedule replayed from graphs and launched step by
+    step gives identical accumulators."""
+    g = make_batch(rf, ora, tile=256, blocks_per_cu=8, graph_steps=4)
+    e = make_batch(rf, ora, tile=256, blocks_per_cu=8, graph_steps=0)
+    for x in (g, e):
+        x.stats_config(2)
+        x.step(16)
+    for r in range(len(REPLICAS)):
+        assert same_stats(g[r].stats(), e[r].stats()), r
+
+
+def test_batch_parity_change_moves_every_replica(rf, ora):
+    """A restart at a step count of the other parity: every replica keeps its
+    state through the change of AA layout (one scratch plane for the batch)."""
+    b = make_batch(rf, ora)
+    b.step(4)
+    snap = [b[r].populations() for r in range(len(REPLICAS))]
+    b.t = 7
+    assert b.t == 7 and all(b[r].t == 7 for r in range(len(REPLICAS)))
+    for r in range(len(REPLICAS)):
+        assert bool((b[r].populations() == snap[r]).all()), r
+    b.step(2)
+    b.sync()
