@@ -184,10 +184,16 @@ def precision_full(dims=(512, 512, 512), kts=(1e-4, 1e-5, 1e-6), steps=1000, eve
             "start": "thermal fluctuations on Taylor-Green A=0.01", "rows": out}
 
 
-def run_batch(storage, steps=200, graph_steps=20):
+def run_batch(storage, steps=2000, sep_steps=200, graph_steps=20, stats_steps=2000, stats_every=10):
     """The 64-replica workload: boxes 32^3..96^3, tau in [0.55, 1.2], kT in
     [1e-6, 1e-4], Taylor-Green A = 0.01 per box; aggregate MLUPS of the
-    persistent hipGraph-replayed launch and of one launch per replica."""
+    persistent hipGraph-replayed launch over `steps` steps and of one launch
+    per replica over `sep_steps`.  Then equipartition of the batched form:
+    every replica restarted from thermal fluctuations at rest and run
+    `stats_steps` batched steps with statistics every `stats_every` steps;
+    ER(u^2) = <u^2> / (3 kT / rho0) and ER(rho) = <d rho^2> / (rho0 kT / cs2)
+    per replica."""
+    import numpy as np
     import torch
 
     import paper_2507_08820_amd as rf
@@ -207,7 +213,6 @@ def run_batch(storage, steps=200, graph_steps=20):
     b.sync()
     ms = b.time_steps(steps)
     b.sync()
-    sep_steps = max(10, steps // 10)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -218,10 +223,31 @@ def run_batch(storage, steps=200, graph_steps=20):
     b.sync()
     n = b.nodes
     out = {"replicas": len(reps), "nodes": n, "tile": tile, "blocks_per_cu": bpc,
-           "graph_steps": graph_steps,
+           "graph_steps": graph_steps, "steps": steps,
            "mlups_persistent_graph": round(n * steps / (ms * 1e-3) / 1e6, 1),
            "mlups_one_launch_per_replica": round(n * sep_steps / (ms_sep * 1e-3) / 1e6, 1)}
     out["gain"] = round(out["mlups_persistent_graph"] / out["mlups_one_launch_per_replica"], 3)
+    # equipartition of every replica in the batched form
+    for r in range(len(reps)):
+        b[r].init_thermal()
+    b.stats_config(stats_every)
+    b.step(stats_steps)
+    b.sync()
+    er_u2, er_rho = [], []
+    for r, t in enumerate(table):
+        st = b[r].stats()
+        m = st["samples"] * st["nodes"]
+        er_u2.append(float(np.sum(st["sum_u2"]) / m / (3 * t["kT"])))
+        var_rho = st["sum_drho2"] / m - (st["sum_drho"] / m) ** 2
+        er_rho.append(float(var_rho / (3 * t["kT"])))
+    er_u2, er_rho = np.array(er_u2), np.array(er_rho)
+    out["equipartition"] = {
+        "steps": stats_steps, "stats_every": stats_every, "start": "thermal fluctuations at rest",
+        "er_u2_mean": round(float(er_u2.mean()), 5), "er_u2_min": round(float(er_u2.min()), 5),
+        "er_u2_max": round(float(er_u2.max()), 5),
+        "er_rho_mean": round(float(er_rho.mean()), 5), "er_rho_min": round(float(er_rho.min()), 5),
+        "er_rho_max": round(float(er_rho.max()), 5),
+        "max_abs_error": round(float(max(np.abs(er_u2 - 1).max(), np.abs(er_rho - 1).max())), 5)}
     log(f"batch {storage}: {out}")
     b.close()
     torch.cuda.empty_cache()
@@ -305,6 +331,130 @@ def table3_run(dims=(256, 256, 256), taus=TABLE3_TAUS, bgk_taus=(0.5005,) + TABL
             torch.cuda.empty_cache()
     return {"box": list(dims), "kT": kT, "burn_in": burn, "steps": steps, "stats_every": every,
             "sk_every": sk_every, "rows": rows}
+
+
+# Field groups of Table III and their FDT variances per component (rho0 = 1,
+# mu = kT / cs2): rho, the three rho u_a, the three Pi_aa, the three Pi_ab.
+ER_GROUPS = (("rho", ("rho",), 1.0), ("sum_rho_u", ("jx", "jy", "jz"), None),
+             ("sum_Pi_aa", ("pi_xx", "pi_yy", "pi_zz"), 2.0 / 9.0),
+             ("sum_Pi_ab", ("pi_xy", "pi_xz", "pi_yz"), 1.0 / 9.0))
+
+
+def er_from_stats(s, kT):
+    """ER of each Table III group from the FP64 step statistics (every sampled
+    step, variance about the mean over all samples)."""
+    import numpy as np
+    mu = kT / (1.0 / 3.0)
+    n = s["samples"] * s["nodes"]
+    var = lambda a, b: b / n - (a / n) ** 2
+    return {"rho": var(s["sum_drho"], s["sum_drho2"]) / mu,
+            "sum_rho_u": float(np.sum(var(s["sum_j"], s["sum_j2"]))) / (3 * kT),
+            "sum_Pi_aa": float(np.sum(var(s["sum_pi"][:3], s["sum_pi2"][:3]))) / (3 * mu * 2 / 9),
+            "sum_Pi_ab": float(np.sum(var(s["sum_pi"][3:], s["sum_pi2"][3:]))) / (3 * mu / 9)}
+
+
+def group_theory(kT, weight):
+    mu = kT / (1.0 / 3.0)
+    return kT if weight is None else mu * weight
+
+
+def table3_protocol(dims=(256, 256, 256), reg_taus=(0.5001, 0.505, 0.51, 1.0, 10.0, 50.0, 100.0),
+                    bgk_taus=(0.505, 0.51, 10.0, 50.0, 100.0), kT=1.0 / 3000.0, burn=2000, steps=500000,
+                    blocks=10, every=50, snap_every=5000, out_path=None, storage="f32"):
+    """Table III and Figs. 1-2 of Sec. III at the paper's protocol: periodic box
+    at rest, rho0 = 1, kT = 1/3000, ghosts at tau = 1, `steps` measured steps
+    with a snapshot of rho, rho u and Pi every `snap_every` steps.  Thermalised
+    start and `burn` unmeasured steps first.  Two estimators of each ER:
+      - "snapshots": the paper's, the spatial variance of each snapshot about
+        its own mean (from the structure-factor shell sums: by Parseval the sum
+        over all n != 0 of |dm^(n)|^2 is N times that variance), averaged over
+        the snapshots;
+      - "dense": the step statistics sampled every `every` steps.
+    The run is cut into `blocks` equal blocks; each ER is the mean over blocks
+    and its standard error the blocks' standard deviation over sqrt(blocks).
+    The |k|-resolved ratio of each group (Fig. 1) is the snapshot shell sums
+    over the whole run; Fig. 2 is its minimum and maximum over 4 <= |k| <= 64.
+    Each finished tau is appended as one JSON line to out_path."""
+    import numpy as np
+    import torch
+
+    import paper_2507_08820_amd as rf
+
+    paper = paper_table3()
+    names = [g[0] for g in ER_GROUPS]
+    n_nodes = dims[0] * dims[1] * dims[2]
+    per_block = steps // blocks
+    assert per_block % snap_every == 0 and per_block % every == 0
+    rows = []
+    for model, tlist in (("reg", reg_taus), ("bgk", bgk_taus)):
+        for tau in tlist:
+            t0 = time.time()
+            lat = rf.Lattice(dims, kT=kT, tau=tau, tau_bulk=tau, tau_ghost=1.0, model=model, seed=7,
+                             storage=storage)
+            lat.init_thermal()
+            lat.step(burn)
+            lat.stats_config(every)
+            dense = {k: [] for k in names}
+            snaps = {k: [] for k in names}
+            shell = None
+            stable = True
+            for b in range(blocks):
+                lat.reset_stats()
+                lat.reset_sk()
+                for _ in range(per_block // snap_every):
+                    lat.step(snap_every)
+                    lat.sk_sample()
+                try:
+                    lat.sync()
+                except rf.RFLBMError:
+                    stable = False
+                    break
+                for k, v in er_from_stats(lat.stats(), kT).items():
+                    dense[k].append(v)
+                fields = {f: lat.sk(f) for f in rf.FIELDS}
+                counts, ns = fields["rho"][1], fields["rho"][2]
+                if shell is None:
+                    shell = {f: np.zeros_like(fields[f][0]) for f in rf.FIELDS}
+                    shell_counts, shell_samples = counts.copy(), 0
+                shell_samples += ns
+                for f in rf.FIELDS:
+                    shell[f] += fields[f][0]
+                for name, comps, weight in ER_GROUPS:
+                    tot = sum(fields[f][0].sum() for f in comps)
+                    snaps[name].append(tot / (n_nodes * ns) / (len(comps) * group_theory(kT, weight)))
+                log(f"table3 {model} tau={tau}: block {b + 1}/{blocks} ({(b + 1) * per_block} steps, "
+                    f"{time.time() - t0:.0f} s) snapshots ER {[round(snaps[k][-1], 4) for k in names]}")
+            row = {"model": model, "tau": tau, "stable": stable}
+            if stable:
+                for est, vals in (("dense", dense), ("snapshots", snaps)):
+                    row[est] = {k: [round(float(np.mean(v)), 5), round(float(np.std(v, ddof=1) / np.sqrt(len(v))), 5)]
+                                for k, v in vals.items()}
+                k = np.arange(len(shell_counts))
+                sel = shell_counts > 0
+                spectra = {}
+                for name, comps, weight in ER_GROUPS:
+                    er_k = np.full(len(k), np.nan)
+                    er_k[sel] = (sum(shell[f][sel] for f in comps) / shell_counts[sel] / shell_samples
+                                 / (len(comps) * group_theory(kT, weight)))
+                    spectra[name] = [None if not np.isfinite(v) else round(float(v), 4) for v in er_k]
+                    band = er_k[(k >= 4) & (k <= 64) & sel]
+                    row.setdefault("fig2_min_max_k4_64", {})[name] = [round(float(band.min()), 4),
+                                                                      round(float(band.max()), 4)]
+                row["fig1_er_by_shell"] = spectra
+                row["shell_counts"] = [int(c) for c in shell_counts]
+            row["paper"] = (dict(zip(names, paper[(model, tau)])) if (model, tau) in paper
+                            and abs(kT - 1.0 / 3000.0) < 1e-12 else None)
+            row["seconds"] = round(time.time() - t0, 1)
+            log(f"table3 {model} tau={tau}: {json.dumps({k: row.get(k) for k in ('stable', 'snapshots', 'paper')})}")
+            if out_path:
+                with open(out_path, "a") as fh:
+                    fh.write(json.dumps(row) + "\n")
+            rows.append(row)
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+    return {"box": list(dims), "kT": kT, "burn_in": burn, "steps": steps, "blocks": blocks,
+            "stats_every": every, "snapshot_every": snap_every, "storage": storage, "rows": rows}
 
 
 VALU_CMD = ("rocprofv3 --pmc VALUBusy SQ_INSTS_VALU -d <out>/prof_valu_{s} -o valu --output-format csv "
@@ -566,14 +716,25 @@ def copy_ceiling(nbytes=4 << 30, reps=20):
     return 2 * nbytes / sec / 1e9
 
 
-def cpu_baseline(min_seconds=10.0, max_steps=200):
-    """The FP64 oracle as it stands on the host cores, on a 128^3 sample of the
-    same workload (Taylor-Green, tau 0.6, kT 1e-5): whole steps until at least
-    min_seconds have passed."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(size, min_seconds=10.0, max_steps=200):
+    """The FP64 oracle as it stands on a size^3 sample of the benchmark workload
+    (Taylor-Green, tau 0.6, kT 1e-5, the same noise): whole steps until at least
+    min_seconds have passed.  Returns (MLUPS, threads, steps, seconds)."""
     import oracle
     import workloads as wl
 
-    dims = (128, 128, 128)
+    dims = (size, size, size)
     rho, u = wl.taylor_green(dims, amp=0.01)
     f = oracle.init_equilibrium(dims, rho, u)
     p = oracle.make_params(kT=1e-5, tau_shear=0.6, tau_bulk=0.6, seed=3)
@@ -583,10 +744,32 @@ def cpu_baseline(min_seconds=10.0, max_steps=200):
         f = oracle.step(p, dims, f, steps)
         steps += 1
     dt = time.perf_counter() - t0
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"128^3 Taylor-Green box (same tau, kT, noise), {steps} steps, FP64, "
-                      f"{dt:.1f} s"}
+    return n * steps / dt / 1e6, oracle.threads(), steps, dt
+
+
+def cpu_baseline(min_seconds=10.0):
+    """The oracle on all host threads (128^3 sample) and on one thread (64^3
+    sample, in a child process with OMP_NUM_THREADS=1), with the CPU model."""
+    import subprocess
+
+    mlups, threads, steps, dt = oracle_rate(128, min_seconds)
+    out = {"value": mlups, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"128^3 Taylor-Green box (same tau, kT, noise), {steps} steps, FP64, {dt:.1f} s, "
+                     f"{threads} OpenMP threads",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "64",
+                        "--cpu-baseline-seconds", str(min_seconds)], env=env, capture_output=True, text=True,
+                       timeout=300)
+    if r.returncode == 0:
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["value_1_thread"] = one["mlups"]
+        out["sample_1_thread"] = (f"64^3 sample of the same workload, {one['steps']} steps, FP64, "
+                                  f"{one['seconds']:.1f} s, {one['threads']} thread")
+    else:
+        out["value_1_thread"] = None
+        out["sample_1_thread"] = "one-thread run failed: " + r.stderr[-300:]
+    return out
 
 
 def main():
@@ -606,8 +789,16 @@ def main():
                     help="with --table3: BGK-FLBM taus to run ('' for none)")
     ap.add_argument("--table3-kT", type=float, default=1.0 / 3000.0,
                     help="with --table3: temperature (the paper's 1/3000 by default)")
-    ap.add_argument("--table3-steps", type=int, default=20000,
-                    help="with --table3: measured steps (400 statistics samples, 40 S(k) snapshots)")
+    ap.add_argument("--table3-steps", type=int, default=None,
+                    help="measured steps; --table3: 20 000 (400 statistics samples, 40 S(k) snapshots), "
+                         "--table3-protocol: 500 000 (statistics every 50 steps, 100 snapshots)")
+    ap.add_argument("--cpu-baseline-worker", type=int, metavar="SIZE", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0, help=argparse.SUPPRESS)
+    ap.add_argument("--table3-protocol", action="store_true",
+                    help="Table III / Figs. 1-2 at the paper's protocol (256^3, 500 000 steps, 100 snapshots)")
+    ap.add_argument("--table3-size", type=int, default=256)
+    ap.add_argument("--table3-blocks", type=int, default=10)
+    ap.add_argument("--table3-out", metavar="PATH", help="append one JSON line per finished tau")
     ap.add_argument("--profile-storage", default="f32", choices=["f32", "f16", "bf16"],
                     help="with --profile: storage of the profiled workload")
     ap.add_argument("--profile-batch", choices=["f32", "f16"],
@@ -635,6 +826,10 @@ def main():
         sys.exit(2)
 
     dims = (args.size,) * 3
+    if args.cpu_baseline_worker:
+        mlups, threads, steps, dt = oracle_rate(args.cpu_baseline_worker, args.cpu_baseline_seconds)
+        print(json.dumps({"mlups": mlups, "threads": threads, "steps": steps, "seconds": dt}))
+        return
     if args.summarize:
         print(summarize_profiles(args.summarize))
         return
@@ -659,13 +854,26 @@ def main():
     if args.precision512:
         print(json.dumps(precision_full()))
         return
+    if args.table3_protocol:
+        kw = {}
+        if args.table3_taus is not None:
+            kw["reg_taus"] = tuple(float(t) for t in args.table3_taus.split(",") if t)
+        if args.table3_bgk_taus is not None:
+            kw["bgk_taus"] = tuple(float(t) for t in args.table3_bgk_taus.split(",") if t)
+        steps = args.table3_steps or 500000
+        n = args.table3_size
+        print(json.dumps(table3_protocol(dims=(n, n, n), kT=args.table3_kT, steps=steps,
+                                         blocks=args.table3_blocks, every=50,
+                                         snap_every=steps // (10 * args.table3_blocks),
+                                         out_path=args.table3_out, **kw)))
+        return
     if args.table3:
         kw = {}
         if args.table3_taus is not None:
             kw["taus"] = tuple(float(t) for t in args.table3_taus.split(",") if t)
         if args.table3_bgk_taus is not None:
             kw["bgk_taus"] = tuple(float(t) for t in args.table3_bgk_taus.split(",") if t)
-        steps = args.table3_steps
+        steps = args.table3_steps or 20000
         print(json.dumps(table3_run(kT=args.table3_kT, steps=steps, every=steps // 400, sk_every=steps // 40,
                                     **kw)))
         return
@@ -695,6 +903,8 @@ def main():
         extra["noise_cost_factor"] = round(extra["reg_lbm_kT0_f32"]["mlups"] / main_run["mlups"], 3)
         extra["stats_cost_factor"] = round(extra["f32_stats_every_step"]["mlups"] / main_run["mlups"], 3)
         extra["u2_over_kT_by_storage_128cube"] = precision_study()
+        # the headline 512^3 Taylor-Green workload, same noise for every storage
+        extra["precision_512_taylor_green"] = precision_full(kts=(1e-5,), steps=200, every=10, sk_every=50)
         extra["batch64_f32"] = run_batch("f32")
         extra["batch64_f16"] = run_batch("f16")
         cc = copy_ceiling()

@@ -225,3 +225,24 @@ def test_ghost_rate_er_matches_linear_theory(rf, ora, model, omega_g):
             assert val < 0.98, (key, val)  # the reading's deficit is resolved
         else:
             assert abs(val - 1.0) < 1e-9, (key, val)
+
+
+def test_table3_protocol_reduced_box(rf):
+    """The paper-protocol Table III runner on a reduced box (64^3, tau = 1,
+    kT = 1/3000, 5 blocks of 4000 steps, a snapshot every 1000 steps): every
+    ER of Table III, from the snapshots (the paper's estimator) and from the
+    dense step statistics, is 1 within 4 block standard errors plus 0.3 %
+    (the size of the non-linear bias at this temperature), and the
+    |k|-resolved momentum ratio stays within 5 % of 1 on shells 4..27."""
+    import bench
+
+    res = bench.table3_protocol(dims=(64, 64, 64), reg_taus=(1.0,), bgk_taus=(), burn=500, steps=20000,
+                                blocks=5, every=50, snap_every=1000)
+    row = res["rows"][0]
+    assert row["stable"]
+    print(f"[gpu] table3 64^3 tau=1: {row['snapshots']} {row['dense']}", flush=True)
+    for est in ("snapshots", "dense"):
+        for name, (mean, se) in row[est].items():
+            assert abs(mean - 1.0) <= 4 * se + 3e-3, (est, name, mean, se)
+    spec = np.array([np.nan if v is None else v for v in row["fig1_er_by_shell"]["sum_rho_u"]])
+    assert np.all(np.abs(spec[4:28] - 1.0) < 0.05), spec[4:28]
