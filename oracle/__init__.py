@@ -82,7 +82,7 @@ class Params(ctypes.Structure):
 
 
 def make_params(kT=0.0, tau_shear=1.0, tau_bulk=None, tau_ghost=1.0, seed=1, stream_id=0,
-                rounds=10, model="reg", rho0=1.0) -> Params:
+                rounds=7, model="reg", rho0=1.0) -> Params:
     p = Params()
     p.rho0 = rho0
     p.kT = kT

@@ -50,11 +50,13 @@
  *   - the random numbers: Philox4x32-R (Salmon, Moraes, Dror and Shaw, SC'11,
  *     "Parallel random numbers: as easy as 1, 2, 3") with key (seed low word,
  *     seed high word) and counter (node, step, call j = 0..5, stream id); word
- *     w of call j is uniform q = 4j + w, U_q = ((word >> 8) + 1) 2^-24 in
- *     (0, 1], a value single precision holds exactly for every word; the
- *     Box-Muller transform of pairs (U_2p, U_2p+1) gives z_2p = R cos(theta),
- *     z_2p+1 = R sin(theta), R = sqrt(-2 ln U_2p), theta = 2 pi U_2p+1; mode k
- *     (4..26) receives r_k = z_(k-4); z_23 is unused.
+ *     w of call j is uniform q = 4j + w, made of the word's top 23 bits
+ *     b = word >> 9: a radius uniform (q even) U_q = 1 - b 2^-23 in
+ *     [2^-23, 1], an angle uniform (q odd) U_q = b 2^-23 in [0, 1), both
+ *     held exactly in single precision; the Box-Muller transform of pairs
+ *     (U_2p, U_2p+1) gives z_2p = R cos(theta), z_2p+1 = R sin(theta),
+ *     R = sqrt(-2 ln U_2p), theta = 2 pi U_2p+1; mode k (4..26) receives
+ *     r_k = z_(k-4); z_23 is unused.
  *
  * Pins.  The Philox bit stream is pinned to the published definition of the
  * round by inversion: the tests undo R rounds of that definition (its odd
@@ -237,6 +239,14 @@ void ora_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t round
   out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
+/* Uniform number w of a Philox call from its word: the top 23 bits
+ * b = word >> 9, as 1 - b 2^-23 in [2^-23, 1] for a radius (w even, never 0,
+ * so the logarithm is finite) or b 2^-23 in [0, 1) for an angle (w odd). */
+static double uniform_of_word(uint32_t word, int w) {
+  const double b = (double)(word >> 9) / 8388608.0;
+  return (w % 2 == 0) ? 1.0 - b : b;
+}
+
 /* The 24 uniforms of one (node, step, stream) and their 24 Box-Muller normals.
  * r[k - 4] for k = 4..26 are the 23 normals the update uses. */
 void ora_uniforms(uint64_t seed, uint32_t stream_id, uint32_t rounds, uint32_t node, uint32_t step,
@@ -246,7 +256,7 @@ void ora_uniforms(uint64_t seed, uint32_t stream_id, uint32_t rounds, uint32_t n
     const uint32_t ctr[4] = {node, step, j, stream_id};
     uint32_t words[4];
     ora_philox4x32(ctr, key, rounds, words);
-    for (int w = 0; w < 4; ++w) u[4 * j + w] = ((double)(words[w] >> 8) + 1.0) / 16777216.0;
+    for (int w = 0; w < 4; ++w) u[4 * j + w] = uniform_of_word(words[w], w);
   }
 }
 
@@ -510,7 +520,7 @@ int ora_init_thermal(const ora_params* p, int32_t nx, int32_t ny, int32_t nz, co
       const uint32_t ctr[4] = {(uint32_t)n, 0xFFFFFFFFu, j, p->stream_id};
       uint32_t words[4];
       ora_philox4x32(ctr, key, p->rounds, words);
-      for (int w = 0; w < 4; ++w) uni[4 * j + w] = ((double)(words[w] >> 8) + 1.0) / 16777216.0;
+      for (int w = 0; w < 4; ++w) uni[4 * j + w] = uniform_of_word(words[w], w);
     }
     for (int q = 0; q < 14; ++q) {
       const double radius = sqrt(-2.0 * log(uni[2 * q]));

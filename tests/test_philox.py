@@ -1,11 +1,12 @@
 """Checks of the oracle's counter-based normal generator.
 
 The paper does not name its random number generator.  This build uses
-Philox4x32-R (Salmon et al., SC'11) with Box-Muller.  The bit stream is pinned
+Philox4x32-R (Salmon et al., SC'11; R = 7 by default, 10 optional) with
+Box-Muller.  The bit stream is pinned
 to the published definition of the round without any known-answer vectors:
 undoing R rounds of that definition (its multipliers are odd, hence invertible
 mod 2^32) must give back the counter of every draw.  Also checked: the uniforms
-lie on the 24-bit grid and are uniform, the normals have the moments and
+lie on the 23-bit grids and are uniform, the normals have the moments and
 distribution of N(0, 1), the Box-Muller pairing follows the documented counter
 layout, and draws at neighbouring counters (node, step, call) are uncorrelated.
 """
@@ -14,18 +15,26 @@ import pytest
 from scipy import stats
 
 
-def draw(ora, nodes, step=0, seed=1, stream=0, rounds=10):
+def draw(ora, nodes, step=0, seed=1, stream=0, rounds=7):
     return np.array([ora.normals(seed, stream, rounds, n, step) for n in nodes])
 
 
-def test_uniforms_on_24_bit_grid(ora):
-    u = np.concatenate([ora.uniforms(7, 0, 10, n, 3) for n in range(2000)])
-    q = u * 2 ** 24 - 1
-    np.testing.assert_array_equal(q, np.round(q))
-    assert u.min() > 0 and u.max() <= 1
-    # every value is exact in single precision (24-bit significand)
+def test_uniforms_on_23_bit_grid(ora):
+    """Radius uniforms (even positions) lie on the grid 1 - b 2^-23 in
+    [2^-23, 1] (never 0, so the logarithm is finite), angle uniforms (odd
+    positions) on b 2^-23 in [0, 1), b a 23-bit integer; every value is exact
+    in single precision, and both sets are uniform."""
+    u = np.array([ora.uniforms(7, 0, 10, n, 3) for n in range(2000)])
+    rad, ang = u[:, 0::2].ravel(), u[:, 1::2].ravel()
+    for b in ((1.0 - rad) * 2 ** 23, ang * 2 ** 23):
+        np.testing.assert_array_equal(b, np.round(b))
+        assert b.min() >= 0 and b.max() <= 2 ** 23 - 1
+    assert rad.min() >= 2.0 ** -23 and rad.max() <= 1 and ang.min() >= 0 and ang.max() < 1
     np.testing.assert_array_equal(u.astype(np.float32).astype(np.float64), u)
-    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    for x in (rad, ang):
+        assert stats.kstest(x, "uniform").pvalue > 1e-4
+    # the draws spread over the whole range
+    assert (1.0 - rad).max() > 0.999 and ang.max() > 0.999 and ang.min() < 1e-3
 
 
 def test_box_muller_pairing(ora):
@@ -54,34 +63,35 @@ def test_per_mode_normals_are_standard(ora):
         assert abs(z[:, k].var() - 1) < 5 * np.sqrt(2 / len(z))
 
 
+@pytest.mark.parametrize("rounds", [7, 10])
 @pytest.mark.parametrize("which", ["node", "step", "mode", "stream"])
-def test_neighbouring_counters_uncorrelated(ora, which):
+def test_neighbouring_counters_uncorrelated(ora, which, rounds):
     m = 8000
     if which == "node":
-        a, b = draw(ora, range(0, 2 * m, 2)), draw(ora, range(1, 2 * m, 2))
+        a, b = draw(ora, range(0, 2 * m, 2), rounds=rounds), draw(ora, range(1, 2 * m, 2), rounds=rounds)
     elif which == "step":
-        a, b = draw(ora, range(m), step=5), draw(ora, range(m), step=6)
+        a, b = draw(ora, range(m), step=5, rounds=rounds), draw(ora, range(m), step=6, rounds=rounds)
     elif which == "stream":
-        a, b = draw(ora, range(m), stream=0), draw(ora, range(m), stream=1)
+        a, b = draw(ora, range(m), stream=0, rounds=rounds), draw(ora, range(m), stream=1, rounds=rounds)
     else:
-        z = draw(ora, range(m))
+        z = draw(ora, range(m), rounds=rounds)
         a, b = z[:, :-1], z[:, 1:]
     r = np.corrcoef(a.ravel(), b.ravel())[0, 1]
     assert abs(r) < 5 / np.sqrt(a.size)
 
 
 def test_key_rounds_and_determinism(ora):
-    base = ora.normals(1, 0, 10, 123, 4)
-    np.testing.assert_array_equal(base, ora.normals(1, 0, 10, 123, 4))
-    assert not np.array_equal(base, ora.normals(2, 0, 10, 123, 4))
-    assert not np.array_equal(base, ora.normals(1 + (1 << 32), 0, 10, 123, 4))  # high key word
-    assert not np.array_equal(base, ora.normals(1, 0, 7, 123, 4))
+    base = ora.normals(1, 0, 7, 123, 4)
+    np.testing.assert_array_equal(base, ora.normals(1, 0, 7, 123, 4))
+    assert not np.array_equal(base, ora.normals(2, 0, 7, 123, 4))
+    assert not np.array_equal(base, ora.normals(1 + (1 << 32), 0, 7, 123, 4))  # high key word
+    assert not np.array_equal(base, ora.normals(1, 0, 10, 123, 4))
     out = ora.philox4x32([0, 0, 0, 0], [0, 0], 10)
     assert out.dtype == np.uint32 and np.any(out != 0)
 
 
-def test_seven_round_variant_is_also_normal(ora):
-    z = draw(ora, range(10000), rounds=7)[:, :23].ravel()
+def test_ten_round_variant_is_also_normal(ora):
+    z = draw(ora, range(10000), rounds=10)[:, :23].ravel()
     assert stats.kstest(z, "norm").pvalue > 1e-4
 
 
