@@ -1,7 +1,7 @@
 """Throughput of the fused Reg-FLBM D3Q27 step on one MI355X.
 
 Workload (fixed): 512^3 periodic box, rho0 = 1, tau = 0.6 (all hydrodynamic
-modes), ghosts at tau = 1, kT = 1e-5, Philox4x32-10 noise, Taylor-Green initial
+modes), ghosts at tau = 1, kT = 1e-5, Philox4x32-7 noise, Taylor-Green initial
 velocity of amplitude 0.01, FP32 population storage.  One step = one fused
 stream + collide kernel over the whole box.  The populations are resident in
 HBM before the timed region starts.
@@ -930,7 +930,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"Reg-FLBM D3Q27 {dims[0]}^3 periodic box, Taylor-Green A=0.01, "
-                               "rho0=1, tau=0.6, ghost tau=1, kT=1e-5, Philox4x32-10, FP32 storage",
+                               "rho0=1, tau=0.6, ghost tau=1, kT=1e-5, Philox4x32-7, FP32 storage",
                    "box": list(dims), "tau": 0.6, "kT": 1e-5, "storage": "f32"},
         "roofline": roofline,
         "cpu_baseline": cpu,

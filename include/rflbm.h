@@ -24,11 +24,14 @@
  *   Population arrays exchanged with the caller are FP64, planar:
  *     f[i * N + n], i = 0..26, and hold the pre-collision state f(x, t) at the
  *     current step count t.
- *   Random numbers: Philox4x32 with key (seed low word, seed high word) and
+ *   Random numbers (r_k ~ N(0, 1) of Eq. fluct_phi; the paper leaves the
+ *     generator open): Philox4x32 with key (seed low word, seed high word) and
  *     counter (n, t mod 2^32, j = 0..5, stream_id); word w of call j gives
- *     U = ((w >> 8) + 1) 2^-24; Box-Muller pairs give normal z_q, and mode k
- *     (Table II order, 4..26) receives z_(k-4).  The trajectory is therefore a
- *     function of (params, initial state) only, on any device or host.
+ *     uniform 4 j + w from its top 23 bits b = word >> 9, 1 - b 2^-23 for the
+ *     radius (w even) and b 2^-23 for the angle (w odd) of a Box-Muller pair;
+ *     the pairs give normals z_q, and mode k (Table II order, 4..26) receives
+ *     z_(k-4).  The trajectory is therefore a function of (params, initial
+ *     state) only, on any device or host.
  *   Memory: "device" pointers are HIP device allocations (for instance torch
  *     tensors on the GPU); "host" pointers are ordinary memory.  Host arrays
  *     are read or written synchronously before the call returns.  Device
@@ -90,7 +93,7 @@ typedef struct {
   int32_t nx, ny, nz;      /* periodic box, each >= 2 (fixed at creation) */
   int32_t storage;         /* rflbm_storage (fixed at creation) */
   int32_t model;           /* rflbm_model */
-  uint32_t philox_rounds;  /* Philox rounds, 7 or 10 (else EINVAL); 10 is the default */
+  uint32_t philox_rounds;  /* Philox rounds, 7 or 10 (else EINVAL); 7 is the default */
   double rho0;             /* reference density > 0 (Sec. III: rho normalised to 1) */
   double kT;               /* k_B T >= 0; 0 gives the deterministic Reg-LBM (Sec. IV) */
   double tau_shear;        /* 1/omega_h on the deviatoric modes k = 4..9, > 1/2; the
@@ -104,7 +107,7 @@ typedef struct {
                               which needs kT > 0 */
 } rflbm_params;
 
-/* Fills p with defaults for an nx x ny x nz box: F32, Reg model, 10 Philox
+/* Fills p with defaults for an nx x ny x nz box: F32, Reg model, 7 Philox
  * rounds, rho0 = 1, kT = 0, every tau = 1, seed 1, stream 0. */
 void rflbm_params_default(rflbm_params* p, int32_t nx, int32_t ny, int32_t nz);
 
@@ -358,7 +361,8 @@ rflbm_status rflbm_batch_autotune(rflbm_batch* b, int32_t trial_steps, const cha
 
 /* Diagnostics.
  * rflbm_rng_normals: for count nodes n = node0 .. node0 + count - 1 at step t,
- * writes the 24 uniforms (FP32, U as above) and the 24 normals (FP32) the step
+ * writes the 24 uniforms (FP32, radius and angle uniforms as above) and the
+ * 24 normals (FP32) the step
  * kernel draws, to device arrays u[24 * count] and z[24 * count] (node-major).
  * rflbm_copy: a plain device-to-device copy kernel of `bytes` bytes (multiple
  * of 16, both pointers 16-byte aligned) on hip_stream, the reference for

@@ -149,7 +149,7 @@ def check(status: int):
 
 
 def make_params(dims, *, storage="f32", model="reg", kT=0.0, tau=1.0, tau_bulk=None,
-                tau_ghost=1.0, rho0=1.0, seed=1, stream_id=0, philox_rounds=10,
+                tau_ghost=1.0, rho0=1.0, seed=1, stream_id=0, philox_rounds=7,
                 storage_scale=0.0) -> Params:
     lib = load_library()
     p = Params()

@@ -309,8 +309,10 @@ rflbm_status lattice_steps(rflbm_lattice* L, int64_t nsteps) {
     a.step = static_cast<uint32_t>(t & 0xffffffffu);
     const bool odd = (t & 1) != 0;
     uint32_t grid = L->launch.grid;  // blocks, hence statistics partials, of the kernel used
-    if (odd && odd_in_rows(L)) {
-      RFLBM_HIP(launch_step_row(L->p.storage, rounds, stats, a, L->stream));
+    if ((odd || stats) && odd_in_rows(L)) {
+      // whole rows: odd steps, and even steps with statistics (one partial per
+      // row; the one-wave even blocks would write one per wave)
+      RFLBM_HIP(launch_step_row(L->p.storage, odd, rounds, stats, a, L->stream));
       grid = row_grid(L->p.ny, L->p.nz);
     } else if (!odd && !stats && rows_pay(L) && L->p.nx % 64 == 0) {
       RFLBM_HIP(launch_step_wave(L->p.storage, rounds, a, L->stream));
@@ -362,7 +364,7 @@ void rflbm_params_default(rflbm_params* p, int32_t nx, int32_t ny, int32_t nz) {
   p->nz = nz;
   p->storage = RFLBM_F32;
   p->model = RFLBM_MODEL_REG;
-  p->philox_rounds = 10;
+  p->philox_rounds = 7;
   p->rho0 = 1.0;
   p->kT = 0.0;
   p->tau_shear = 1.0;

@@ -165,10 +165,11 @@ __global__ void init_thermal_kernel(const GatherArgs g, const double* rho, const
 #pragma unroll
     for (uint32_t j = 0; j < 7; ++j) {
       const Word4 w = philox<R>(Word4{static_cast<uint32_t>(n), 0xFFFFFFFFu, j, sid}, key0, key1);
-      const double u0 = (static_cast<double>(w.w0 >> 8) + 1.0) * 0x1p-24;
-      const double u1 = (static_cast<double>(w.w1 >> 8) + 1.0) * 0x1p-24;
-      const double u2 = (static_cast<double>(w.w2 >> 8) + 1.0) * 0x1p-24;
-      const double u3 = (static_cast<double>(w.w3 >> 8) + 1.0) * 0x1p-24;
+      // radius uniforms 1 - b 2^-23, angle uniforms b 2^-23, b = word >> 9
+      const double u0 = 1.0 - static_cast<double>(w.w0 >> 9) * 0x1p-23;
+      const double u1 = static_cast<double>(w.w1 >> 9) * 0x1p-23;
+      const double u2 = 1.0 - static_cast<double>(w.w2 >> 9) * 0x1p-23;
+      const double u3 = static_cast<double>(w.w3 >> 9) * 0x1p-23;
       const double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
       const double two_pi = 6.283185307179586476925;
       z[4 * j + 0] = ra * cos(two_pi * u1);
@@ -261,7 +262,7 @@ __global__ void rng_kernel(uint32_t key0, uint32_t key1, uint32_t sid, uint32_t 
     box_muller(w.w2, w.w3, r[2], r[3]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      u[static_cast<uint64_t>(t) * 24 + 4 * j + q] = word_to_uniform(ws[q]);
+      u[static_cast<uint64_t>(t) * 24 + 4 * j + q] = (q % 2 == 0) ? radius_uniform(ws[q]) : angle_uniform(ws[q]);
       z[static_cast<uint64_t>(t) * 24 + 4 * j + q] = r[q];
     }
   }

@@ -113,10 +113,11 @@ hipError_t launch_step_wave(int storage, int rounds, const StepArgs& a, hipStrea
 // True when the odd step can run in whole-row blocks: nx a multiple of 64, at
 // most 64 kMaxRowWaves.
 bool row_kernel_fits(uint32_t nx);
-// Odd step, one block per x-row (a.xcd_remap applies to rows); every store is
-// a whole aligned cache line.  With stats, one statistics partial per block of
-// the row_grid(ny, nz) blocks.
-hipError_t launch_step_row(int storage, int rounds, bool stats, const StepArgs& a, hipStream_t stream);
+// A step in whole-row blocks, one block per x-row (a.xcd_remap applies to
+// rows): odd steps with or without statistics (every store a whole aligned
+// cache line), even steps with statistics only.  With stats, one statistics
+// partial per block of the row_grid(ny, nz) blocks.
+hipError_t launch_step_row(int storage, bool odd, int rounds, bool stats, const StepArgs& a, hipStream_t stream);
 // Number of blocks of the whole-row odd step: ny nz rounded up to a multiple of 8.
 uint32_t row_grid(uint32_t ny, uint32_t nz);
 

@@ -10,12 +10,15 @@
 // words advance by Weyl increments between rounds.
 //
 // Use in the step kernel: key = (seed low, seed high), counter =
-// (node, step, call j, stream id), j = 0..5.  Each 32-bit word w gives a
-// uniform U = ((w >> 8) + 1) 2^-24 in (0, 1], exact in FP32.  Words (0, 1) and
-// (2, 3) of a call are Box-Muller pairs: R = sqrt(-2 ln U0), z0 = R cos(2 pi U1),
-// z1 = R sin(2 pi U1).  On gfx950 the hardware sine and cosine take their
-// argument in revolutions, so 2 pi U needs no range reduction, and the hardware
-// logarithm is base 2, so ln U0 = ln 2 log2 U0.
+// (node, step, call j, stream id), j = 0..5.  Words (0, 1) and (2, 3) of a call
+// are Box-Muller pairs, each word giving a uniform from its top 23 bits
+// b = w >> 9: the radius word U0 = 1 - b 2^-23 in [2^-23, 1], the angle word
+// U1 = b 2^-23 in [0, 1); R = sqrt(-2 ln U0), z0 = R cos(2 pi U1),
+// z1 = R sin(2 pi U1).  Both are read off one float: the bits 0x3F800000 | b
+// are X = 1 + b 2^-23 in [1, 2), so U0 = 2 - X (exact) and, since the gfx950
+// sine and cosine take their argument in revolutions and are periodic in it,
+// cos(2 pi U1) is the hardware cosine of X itself.  The hardware logarithm is
+// base 2, so ln U0 = ln 2 log2 U0.
 #pragma once
 #include <cstdint>
 #include <hip/hip_runtime.h>
@@ -60,10 +63,16 @@ __host__ __device__ __forceinline__ Word4 philox(Word4 c, uint32_t k0, uint32_t 
   return c;
 }
 
-// Uniform in (0, 1] from the top 24 bits of a word; exact in FP32.
-__device__ __forceinline__ float word_to_uniform(uint32_t w) {
-  return fmaf(static_cast<float>(w >> 8), 0x1p-24f, 0x1p-24f);
+// X = 1 + (w >> 9) 2^-23 in [1, 2): the top 23 bits of w as the mantissa of a
+// float of exponent 0 (one bit-field instruction).
+__device__ __forceinline__ float word_to_one_two(uint32_t w) {
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9));
 }
+
+// The radius uniform 1 - (w >> 9) 2^-23 in [2^-23, 1] and the angle uniform
+// (w >> 9) 2^-23 in [0, 1) of a word, exact in FP32.
+__device__ __forceinline__ float radius_uniform(uint32_t w) { return 2.0f - word_to_one_two(w); }
+__device__ __forceinline__ float angle_uniform(uint32_t w) { return word_to_one_two(w) - 1.0f; }
 
 constexpr float kMinus2Ln2 = -1.38629436111989061883f;  // -2 ln 2
 
@@ -71,11 +80,11 @@ constexpr float kMinus2Ln2 = -1.38629436111989061883f;  // -2 ln 2
 // multiplied by sqrt(c / (-2 ln 2)): the radius is sqrt(c log2 U0), so c = -2 ln 2
 // gives standard normals and c = -2 ln 2 rho gives sqrt(rho) times them.
 __device__ __forceinline__ void box_muller_scaled(uint32_t wr, uint32_t wa, float c, float& z0, float& z1) {
-  const float ur = word_to_uniform(wr);
-  const float ua = word_to_uniform(wa);
+  const float ur = radius_uniform(wr);
+  const float turns = word_to_one_two(wa);  // 1 + the angle uniform, in revolutions
   const float rad = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(ur));
-  z0 = rad * __builtin_amdgcn_cosf(ua);
-  z1 = rad * __builtin_amdgcn_sinf(ua);
+  z0 = rad * __builtin_amdgcn_cosf(turns);
+  z1 = rad * __builtin_amdgcn_sinf(turns);
 }
 
 // Standard normal Box-Muller pair.

@@ -265,15 +265,16 @@ __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
 #include "node_body.inc"
 }
 
-// Odd step of one box in whole-row blocks: block b covers the x-row (y, z) of
-// row index y + ny z (blockDim.x = nx, a multiple of 64 up to 1024), so that
-// the +-1 shifts in x stay inside the block and every load and store is a
-// whole aligned cache line (see row_shift).  With STATS, each wave sums its
+// A step of one box in whole-row blocks: block b covers the x-row (y, z) of
+// row index y + ny z (blockDim.x = nx, a multiple of 64 up to 1024).  On odd
+// steps the +-1 shifts in x stay inside the block and every load and store is
+// a whole aligned cache line (see row_shift).  With STATS, each wave sums its
 // nodes' statistics, and the block adds its waves' sums in FP64 (fixed order)
-// into one partial per block, as step_kernel does.
-template <int S, int ROUNDS, bool GEQ, bool STATS>
+// into one partial per block, as step_kernel does; the even step takes this
+// kernel only for statistics (one partial per row instead of one per wave).
+template <int S, int ROUNDS, bool GEQ, bool STATS, bool ODD>
 __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepArgs a) {
-  constexpr bool ODD = true, SMALL_BOX = false, ROW_SHIFT = true, BUFFER_ACCESS = true;
+  constexpr bool SMALL_BOX = false, ROW_SHIFT = ODD, BUFFER_ACCESS = true;
   constexpr bool GHOST_EQ = GEQ, STATS_WAVE = true;
   [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
   [[maybe_unused]] const uint32_t tid = 0;
@@ -290,9 +291,9 @@ __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepA
   }
   const uint32_t x = threadIdx.x;
 #if RFLBM_ROW_GROUP_Y * RFLBM_ROW_GROUP_Z > 1
-  // rows visited in groups of GY x GZ (y, z) so that the 9 row blocks a row
-  // reads from and writes to are in use at about the same time
-  constexpr uint32_t GY = RFLBM_ROW_GROUP_Y, GZ = RFLBM_ROW_GROUP_Z;
+  // odd steps: rows visited in groups of GY x GZ (y, z) so that the 9 row
+  // blocks a row reads from and writes to are in use at about the same time
+  constexpr uint32_t GY = ODD ? RFLBM_ROW_GROUP_Y : 1, GZ = ODD ? RFLBM_ROW_GROUP_Z : 1;
   uint32_t y, z;
   {
     const uint32_t per_zgroup = a.ny * GZ;
@@ -464,10 +465,10 @@ hipError_t launch_t(const StepArgs& a, const Launch& l, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int S, int R, bool ST>
+template <int S, int R, bool ST, bool ODD>
 void launch_row_g(const StepArgs& a, dim3 g, dim3 blk, hipStream_t s) {
-  if (a.ghost_eq) hipLaunchKernelGGL((step_row_kernel<S, R, true, ST>), g, blk, 0, s, a);
-  else hipLaunchKernelGGL((step_row_kernel<S, R, false, ST>), g, blk, 0, s, a);
+  if (a.ghost_eq) hipLaunchKernelGGL((step_row_kernel<S, R, true, ST, ODD>), g, blk, 0, s, a);
+  else hipLaunchKernelGGL((step_row_kernel<S, R, false, ST, ODD>), g, blk, 0, s, a);
 }
 
 template <int S, int R>
@@ -493,16 +494,23 @@ hipError_t launch_s(bool odd, int rounds, bool stats, const StepArgs& a, const L
   return stats ? launch_r<S, false, true>(rounds, a, l, s) : launch_r<S, false, false>(rounds, a, l, s);
 }
 
-template <int S, bool ST>
+template <int S, bool ST, bool ODD>
 hipError_t launch_row_s(int rounds, const StepArgs& a, uint32_t grid, hipStream_t s) {
   const dim3 g(grid), blk(a.nx);
   switch (rounds) {
-    case 0: launch_row_g<S, 0, ST>(a, g, blk, s); break;
-    case 7: launch_row_g<S, 7, ST>(a, g, blk, s); break;
-    case 10: launch_row_g<S, 10, ST>(a, g, blk, s); break;
+    case 0: launch_row_g<S, 0, ST, ODD>(a, g, blk, s); break;
+    case 7: launch_row_g<S, 7, ST, ODD>(a, g, blk, s); break;
+    case 10: launch_row_g<S, 10, ST, ODD>(a, g, blk, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The even whole-row kernel runs only with statistics.
+template <int S>
+hipError_t launch_row_st(bool odd, bool stats, int rounds, const StepArgs& a, uint32_t grid, hipStream_t s) {
+  if (!odd) return stats ? launch_row_s<S, true, false>(rounds, a, grid, s) : hipErrorInvalidConfiguration;
+  return stats ? launch_row_s<S, true, true>(rounds, a, grid, s) : launch_row_s<S, false, true>(rounds, a, grid, s);
 }
 
 template <int S>
@@ -538,18 +546,15 @@ uint32_t row_grid(uint32_t ny, uint32_t nz) {
   return static_cast<uint32_t>((rows + 7) / 8 * 8);
 }
 
-hipError_t launch_step_row(int storage, int rounds, bool stats, const StepArgs& a, hipStream_t stream) {
+hipError_t launch_step_row(int storage, bool odd, int rounds, bool stats, const StepArgs& a, hipStream_t stream) {
   if (!row_kernel_fits(a.nx)) return hipErrorInvalidConfiguration;
   const uint64_t rows = static_cast<uint64_t>(a.ny) * a.nz;
   if (rows >= (1ull << 31)) return hipErrorInvalidConfiguration;
   const uint32_t grid = row_grid(a.ny, a.nz);
   switch (storage) {
-    case kF32: return stats ? launch_row_s<kF32, true>(rounds, a, grid, stream)
-                            : launch_row_s<kF32, false>(rounds, a, grid, stream);
-    case kF16: return stats ? launch_row_s<kF16, true>(rounds, a, grid, stream)
-                            : launch_row_s<kF16, false>(rounds, a, grid, stream);
-    case kBF16: return stats ? launch_row_s<kBF16, true>(rounds, a, grid, stream)
-                             : launch_row_s<kBF16, false>(rounds, a, grid, stream);
+    case kF32: return launch_row_st<kF32>(odd, stats, rounds, a, grid, stream);
+    case kF16: return launch_row_st<kF16>(odd, stats, rounds, a, grid, stream);
+    case kBF16: return launch_row_st<kBF16>(odd, stats, rounds, a, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -117,7 +117,7 @@ def test_batch_validation():
     assert lib.rflbm_batch_required_bytes(3, arr) > 0
     arr[1] = rf.make_params((16, 4, 4), kT=1e-5, storage="f16")
     assert lib.rflbm_batch_required_bytes(3, arr) == 0  # mixed storage
-    arr[1] = rf.make_params((16, 4, 4), kT=1e-5, philox_rounds=7)
+    arr[1] = rf.make_params((16, 4, 4), kT=1e-5, philox_rounds=10)
     assert lib.rflbm_batch_required_bytes(3, arr) == 0  # mixed rounds
     arr[1] = rf.make_params((16, 4, 4), tau=0.5)
     assert lib.rflbm_batch_required_bytes(3, arr) == 0  # invalid replica
