@@ -457,14 +457,23 @@ def table3_protocol(dims=(256, 256, 256), reg_taus=(0.5001, 0.505, 0.51, 1.0, 10
             "stats_every": every, "snapshot_every": snap_every, "storage": storage, "rows": rows}
 
 
-VALU_CMD = ("rocprofv3 --pmc VALUBusy SQ_INSTS_VALU -d <out>/prof_valu_{s} -o valu --output-format csv "
-            "-- python3 bench.py --profile --profile-storage {s}")
+VALU_CMD = ("rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU -d <out>/prof_valu_{s} -o valu --output-format csv "
+             "-- python3 bench.py --profile --profile-storage {s}")
+# Issue rate of plain FP32 vector instructions measured on the box (a probe of
+# eight independent FMA chains per lane): 97.5 lanes per cycle per CU at the
+# 2.4 GHz peak clock, i.e. one wave64 instruction per 2.63 cycles per SIMD
+# (4 SIMDs per CU).  Transcendental instructions and 32 x 32 -> 64-bit
+# multiply-adds issued 3.2 and about 2.6-4.5 times slower in the same probe.
+FMA_CYCLES_PER_WAVE_INSTR = 4 * 64 / 97.5
+SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
 
 
 def summarize_valu(out_dir, storage, dims=(512, 512, 512)):
     """profiles/step_<storage>_512_valu.txt: per step kernel, the mean over its
-    dispatches of VALUBusy (percent of GPU time the vector ALUs issue) and of
-    the VALU instructions per node (SQ_INSTS_VALU counts wave instructions)."""
+    dispatches of the VALU and SALU instructions per node (SQ_INSTS_* count
+    wave instructions, one node per lane), and the time those VALU
+    instructions take at the measured plain-FP32 issue rate on every SIMD: a
+    lower bound of the kernel time (slower instructions take longer)."""
     import csv
     import glob
 
@@ -482,15 +491,20 @@ def summarize_valu(out_dir, storage, dims=(512, 512, 512)):
         short = m.group(1)
         acc.setdefault(short, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     path = os.path.join(ROOT, "profiles", f"step_{storage}_512_valu.txt")
+    mean = lambda v: sum(v) / len(v) if v else 0.0
     with open(path, "w") as fh:
-        fh.write(f"# VALU activity of the step kernels, 512^3 {storage.upper()} bench workload (4 timed + 2 warm-up steps)\n")
+        fh.write(f"# VALU and SALU instructions of the step kernels, 512^3 {storage.upper()} bench workload "
+                 "(4 timed + 2 warm-up steps)\n")
         fh.write(f"# command: {VALU_CMD.format(s=storage)}\n")
         fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
-        fh.write("kernel | dispatches | VALUBusy % | VALU instructions per node\n")
+        fh.write(f"# issue ms: VALU wave instructions x {FMA_CYCLES_PER_WAVE_INSTR:.2f} cycles / "
+                 f"({SIMDS} SIMDs x {CLOCK_HZ / 1e9:.1f} GHz)\n")
+        fh.write("kernel | dispatches | VALU instructions per node | SALU instructions per node | issue ms\n")
         for k, c in sorted(acc.items()):
-            busy = sum(c.get("VALUBusy", [0.0])) / max(1, len(c.get("VALUBusy", [])))
-            insts = c.get("SQ_INSTS_VALU", [0.0])
-            fh.write(f"{k} | {len(insts)} | {busy:.1f} | {sum(insts) / len(insts) * 64 / n:.0f}\n")
+            valu, salu = c.get("SQ_INSTS_VALU", []), c.get("SQ_INSTS_SALU", [])
+            issue_ms = mean(valu) * FMA_CYCLES_PER_WAVE_INSTR / (SIMDS * CLOCK_HZ) * 1e3
+            fh.write(f"{k} | {len(valu)} | {mean(valu) * 64 / n:.0f} | {mean(salu) * 64 / n:.0f} | "
+                     f"{issue_ms:.3f}\n")
     return path
 
 
@@ -562,14 +576,16 @@ def summarize_profiles(out_dir, dims=(512, 512, 512)):
     copy_bytes = 1 << 30
 
     def kind(name):
-        # FP32, Philox-10, no statistics: the even step is the one-wave kernel,
-        # the odd step the whole-row kernel (the tiled ones when rows are off)
+        # FP32, Philox-7, no statistics: the even step is the one-wave kernel,
+        # the odd step the whole-row kernel (the tiled ones when rows are off);
+        # template arguments <storage, rounds, omega_g = 1, statistics, odd> of
+        # the whole-row kernel, <storage, odd, rounds, statistics, omega_g = 1>
+        # of the tiled one
         if "copy_kernel" in name:
             return "copy"
-        # (the last template argument, every omega_g = 1, may follow)
-        if re.search(r"step_row_kernel<0, 10\b|step_kernel<0, true, 10, false\b", name):
+        if re.search(r"step_row_kernel<0, 7, \w+, false, true>|step_kernel<0, true, 7, false\b", name):
             return "odd"
-        if re.search(r"step_wave_kernel<0, 10\b|step_kernel<0, false, 10, false\b", name):
+        if re.search(r"step_wave_kernel<0, 7\b|step_kernel<0, false, 7, false\b", name):
             return "even"
         return None
 

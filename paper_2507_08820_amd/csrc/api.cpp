@@ -161,6 +161,11 @@ StepArgs step_args(const rflbm_lattice* L) {
   a.tiles_x = (p.nx + L->launch.bx - 1) / L->launch.bx;
   a.tiles_y = (p.ny + L->launch.by - 1) / L->launch.by;
   a.ntiles = a.tiles_x * a.tiles_y * static_cast<uint32_t>(p.nz);
+  const auto fd = [](uint32_t d) { return d >= 2 ? make_fastdiv(d) : FastDiv{0u, 1u}; };
+  a.div_tiles_x = fd(a.tiles_x);
+  a.div_tiles_y = fd(a.tiles_y);
+  a.div_ny = fd(static_cast<uint32_t>(p.ny));
+  a.div_segs = fd(static_cast<uint32_t>(p.nx) / 64u);
   a.xcd_remap = L->xcd_remap ? 1u : 0u;
   a.key0 = static_cast<uint32_t>(p.seed & 0xffffffffu);
   a.key1 = static_cast<uint32_t>(p.seed >> 32);

@@ -5,7 +5,9 @@
 //   s = ceil(log2 d),  m = floor(2^32 (2^s - d) / d) + 1,
 //   q = (t + ((n - t) >> 1)) >> (s - 1),  t = floor(m n / 2^32),
 // exact for every n < 2^32.  Used to turn a flattened node index into (x, y, z)
-// in the batched kernel.  Host-only code may include this header without HIP.
+// in the batched kernel, and block indices into tile or row coordinates in the
+// one-box kernels (there the operands are uniform, so the divisions stay on the
+// scalar unit).  Host-only code may include this header without HIP.
 #pragma once
 #include <cstdint>
 
@@ -37,5 +39,8 @@ RFLBM_HD inline uint32_t fast_div(uint32_t n, FastDiv f) {
 #endif
   return (t + ((n - t) >> 1)) >> (f.s - 1);
 }
+
+// n / d for any d >= 1 (make_fastdiv needs d >= 2; d = 1 is the identity).
+RFLBM_HD inline uint32_t div_by(uint32_t n, uint32_t d, FastDiv f) { return d == 1 ? n : fast_div(n, f); }
 
 }  // namespace rflbm

@@ -40,6 +40,10 @@ struct StepArgs {
   uint32_t tiles_y;      // tiles along y
   uint32_t ntiles;       // tiles_x * tiles_y * nz
   uint32_t xcd_remap;    // 1: give each XCD a contiguous range of tiles
+  FastDiv div_tiles_x;   // division by tiles_x (when tiles_x >= 2)
+  FastDiv div_tiles_y;   // division by tiles_y (when tiles_y >= 2)
+  FastDiv div_ny;        // division by ny
+  FastDiv div_segs;      // division by nx / 64 (when nx / 64 >= 2)
   uint32_t step;         // t mod 2^32 (Philox counter word 1)
   uint32_t key0, key1;   // Philox key
   uint32_t stream_id;    // Philox counter word 3

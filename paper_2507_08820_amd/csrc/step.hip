@@ -144,12 +144,31 @@ __device__ __forceinline__ uint32_t wave_shift_left(uint32_t v) {
   return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), kDppWaveShl1, 0xf, 0xf, false));
 }
 
-// Sum over the 64 lanes of a wave in a fixed order (xor butterfly); every lane
-// gets the same bits.
+// Sum over the 64 lanes of a wave in a fixed order, by DPP lane moves: pairs and
+// quads (quad permutations), half rows and rows of 16 (mirrors), then the four
+// rows through the row broadcasts of lanes 15 and 31; the total ends in lane
+// 63 and is returned to every lane (a scalar read).  Every move writes all
+// rows, lanes without a source reading 0, so each add is one DPP instruction;
+// only lane 63's chain (rows 2 + 3, then rows 0 + 1 from lane 31) is used.
+constexpr int kDppQuadSwapPairs = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwapHalves = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true);
+  return v + __int_as_float(moved);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  v = dpp_add<kDppQuadSwapPairs>(v);
+  v = dpp_add<kDppQuadSwapHalves>(v);
+  v = dpp_add<kDppRowHalfMirror>(v);
+  v = dpp_add<kDppRowMirror>(v);
+  v = dpp_add<kDppRowBcast15>(v);
+  v = dpp_add<kDppRowBcast31>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Whole-row blocks (blockDim.x = nx, so lane = x mod 64): replaces v[i], for
@@ -194,10 +213,10 @@ template <int S, bool ODD, int ROUNDS, bool STATS, bool GEQ>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
   uint32_t tile = blockIdx.x;
   if (a.xcd_remap) tile = (tile & 7u) * (gridDim.x >> 3) + (tile >> 3);
-  const uint32_t tx = tile % a.tiles_x;
-  const uint32_t rest = tile / a.tiles_x;
-  const uint32_t ty = rest % a.tiles_y;
-  const uint32_t z = rest / a.tiles_y;
+  const uint32_t rest = div_by(tile, a.tiles_x, a.div_tiles_x);
+  const uint32_t tx = tile - rest * a.tiles_x;
+  const uint32_t z = div_by(rest, a.tiles_y, a.div_tiles_y);
+  const uint32_t ty = rest - z * a.tiles_y;
   const uint32_t x = tx * blockDim.x + threadIdx.x;
   const uint32_t y = ty * blockDim.y + threadIdx.y;
   const uint32_t tid = threadIdx.x + blockDim.x * threadIdx.y;
@@ -256,11 +275,11 @@ __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
   uint32_t seg = blockIdx.x;
   if (a.xcd_remap) seg = (seg & 7u) * (gridDim.x >> 3) + (seg >> 3);
   const uint32_t per_row = a.nx >> 6;
-  const uint32_t row = seg / per_row;
+  const uint32_t row = div_by(seg, per_row, a.div_segs);
   if (row >= a.ny * a.nz) return;  // the whole block: rounding of the grid to 8
   const uint32_t x = (seg - row * per_row) * 64 + threadIdx.x;
-  const uint32_t y = row % a.ny;
-  const uint32_t z = row / a.ny;
+  const uint32_t z = div_by(row, a.ny, a.div_ny);
+  const uint32_t y = row - z * a.ny;
   const uint32_t step = a.step;
 #include "node_body.inc"
 }

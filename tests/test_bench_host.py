@@ -13,10 +13,10 @@ import pytest
 
 import bench
 
-ODD = "void rflbm::(anonymous namespace)::step_row_kernel<0, 10, true>(rflbm::StepArgs)"
-EVEN = "void rflbm::(anonymous namespace)::step_wave_kernel<0, 10, true>(rflbm::StepArgs)"
+ODD = "void rflbm::(anonymous namespace)::step_row_kernel<0, 7, true, false, true>(rflbm::StepArgs)"
+EVEN = "void rflbm::(anonymous namespace)::step_wave_kernel<0, 7, true>(rflbm::StepArgs)"
 COPY = "void rflbm::(anonymous namespace)::copy_kernel(rflbm::u32x4*, rflbm::u32x4 const*, unsigned long)"
-OTHER = "void rflbm::(anonymous namespace)::step_kernel<0, false, 10, true, true>(rflbm::StepArgs)"
+OTHER = "void rflbm::(anonymous namespace)::step_kernel<0, false, 7, true, true>(rflbm::StepArgs)"
 
 
 def write_csv(path, fields, rows):
@@ -77,25 +77,27 @@ def test_valu_summary(tmp_path, fake_root):
     n = 8 * 8 * 8
     out = tmp_path / "out"
     rows = []
-    for name, per_node, busy in ((EVEN, 711, 68.0), (ODD, 833, 75.0), (OTHER, 763, 100.0)):
+    for name, per_node, salu in ((EVEN, 711, 10), (ODD, 833, 20), (OTHER, 763, 30)):
         for _ in range(3):
             rows.append(dict(Kernel_Name=name, Counter_Name="SQ_INSTS_VALU", Counter_Value=per_node * n / 64))
-            rows.append(dict(Kernel_Name=name, Counter_Name="VALUBusy", Counter_Value=busy))
+            rows.append(dict(Kernel_Name=name, Counter_Name="SQ_INSTS_SALU", Counter_Value=salu * n / 64))
     rows.append(dict(Kernel_Name=COPY, Counter_Name="SQ_INSTS_VALU", Counter_Value=1.0))
     write_csv(str(out / "prof_valu_f32" / "valu_counter_collection.csv"), ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
     path = bench.summarize_valu(str(out), "f32", dims=dims)
     text = open(path).read()
-    assert "step_wave_kernel<0, 10, true> | 3 | 68.0 | 711" in text
-    assert "step_row_kernel<0, 10, true> | 3 | 75.0 | 833" in text
-    assert "step_kernel<0, false, 10, true, true> | 3 | 100.0 | 763" in text
+    # issue time: 711 n / 64 wave instructions x 2.63 cycles / (1024 SIMDs x 2.4 GHz)
+    issue = 711 * n / 64 * bench.FMA_CYCLES_PER_WAVE_INSTR / (1024 * 2.4e9) * 1e3
+    assert f"step_wave_kernel<0, 7, true> | 3 | 711 | 10 | {issue:.3f}" in text
+    assert "step_row_kernel<0, 7, true, false, true> | 3 | 833 | 20 |" in text
+    assert "step_kernel<0, false, 7, true, true> | 3 | 763 | 30 |" in text
     assert "copy_kernel" not in text
 
 
 def test_16bit_trace_summary(tmp_path, fake_root):
     dims = (8, 8, 8)
     out = tmp_path / "out"
-    even = "void rflbm::(anonymous namespace)::step_kernel<1, false, 10, false, true>(rflbm::StepArgs)"
-    odd = "void rflbm::(anonymous namespace)::step_kernel<1, true, 10, false, true>(rflbm::StepArgs)"
+    even = "void rflbm::(anonymous namespace)::step_kernel<1, false, 7, false, true>(rflbm::StepArgs)"
+    odd = "void rflbm::(anonymous namespace)::step_kernel<1, true, 7, false, true>(rflbm::StepArgs)"
     stats = [dict(Name=even, Calls=3, AverageNs=3000.0, MinNs=2990, MaxNs=3010),
              dict(Name=odd, Calls=3, AverageNs=3400.0, MinNs=3390, MaxNs=3410),
              dict(Name=COPY, Calls=1, AverageNs=100.0, MinNs=100, MaxNs=100)]
@@ -110,8 +112,8 @@ def test_16bit_trace_summary(tmp_path, fake_root):
 
 def test_batch_trace_summary(tmp_path, fake_root):
     out = tmp_path / "out"
-    even = "void rflbm::(anonymous namespace)::batch_kernel<0, false, 10, true>(rflbm::BatchArgs)"
-    odd = "void rflbm::(anonymous namespace)::batch_kernel<0, true, 10, true>(rflbm::BatchArgs)"
+    even = "void rflbm::(anonymous namespace)::batch_kernel<0, false, 7, true, false>(rflbm::BatchArgs)"
+    odd = "void rflbm::(anonymous namespace)::batch_kernel<0, true, 7, true, false>(rflbm::BatchArgs)"
     stats = [dict(Name=even, Calls=30, AverageNs=800.0, MinNs=790, MaxNs=810),
              dict(Name=odd, Calls=30, AverageNs=900.0, MinNs=890, MaxNs=910),
              dict(Name="void rflbm::(anonymous namespace)::advance_step(unsigned int*)", Calls=60,
