@@ -1,0 +1,80 @@
+"""The committed record of Table III and Figs. 1-2 (Sec. III) at the paper's
+protocol, `results/table3_protocol_256.json`, as the benchmark's
+`--table3-protocol` runs wrote it on the GPU.
+
+These CPU checks tie the record to the protocol of Sec. III (box, temperature,
+run length, snapshot spacing), to Table III as printed (the `paper` field of
+every row against `tests/golden/table3_er.txt`), and each row to itself: the
+|k|-resolved ratios of Fig. 1 weighted by their shell populations must give back
+the snapshot ratio of the table (Parseval), and the Fig. 2 extremes must be the
+extremes of those spectra over 4 <= |k| <= 64.
+"""
+import json
+import math
+import os
+
+import pytest
+
+import bench
+
+RECORD = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "results", "table3_protocol_256.json")
+GROUPS = ("rho", "sum_rho_u", "sum_Pi_aa", "sum_Pi_ab")
+
+
+@pytest.fixture(scope="module")
+def record():
+    with open(RECORD) as fh:
+        return json.load(fh)
+
+
+def test_protocol_is_the_papers(record):
+    # Sec. III: 256^3, rho = 1, kT = 1/3000, 500 000 steps, a snapshot every 5 000
+    assert record["box"] == [256, 256, 256]
+    assert record["kT"] == pytest.approx(1.0 / 3000.0, rel=1e-12)
+    assert record["steps"] == 500000
+    assert record["snapshot_every"] == 5000
+    assert record["steps"] // record["snapshot_every"] == 100
+    assert record["storage"] == "f32"
+
+
+def test_rows_cover_the_requested_taus(record):
+    got = {(r["model"], r["tau"]) for r in record["rows"]}
+    want = {("reg", t) for t in (0.5001, 0.505, 0.51, 1.0, 10.0, 50.0, 100.0)}
+    want |= {("bgk", t) for t in (0.505, 0.51, 10.0, 50.0, 100.0)}
+    assert want <= got
+    assert all(r["stable"] for r in record["rows"])
+
+
+def test_paper_column_is_table_iii(record):
+    paper = bench.paper_table3()
+    for r in record["rows"]:
+        printed = paper[(r["model"], r["tau"])]
+        assert [r["paper"][g] for g in GROUPS] == printed, (r["model"], r["tau"])
+
+
+def test_standard_errors_present(record):
+    # block standard errors, stored to 5 decimals (the dense ones can round to 0)
+    for r in record["rows"]:
+        for est in ("snapshots", "dense"):
+            for g in GROUPS:
+                mean, err = r[est][g]
+                assert 0.5 < mean < 2.0 and 0.0 <= err < 0.05, (r["model"], r["tau"], est, g)
+
+
+def test_spectra_reproduce_the_table(record):
+    n_nodes = math.prod(record["box"])
+    for r in record["rows"]:
+        counts = r["shell_counts"]
+        # every non-zero wave vector of the box in exactly one shell
+        assert counts[0] == 0 and sum(counts) == n_nodes - 1
+        for g in GROUPS:
+            spec = r["fig1_er_by_shell"][g]
+            assert len(spec) == len(counts)
+            # Parseval: the population-weighted mean of the shell ratios is the
+            # snapshot ratio (shell values are stored to 4 decimals)
+            weighted = sum(c * v for c, v in zip(counts, spec) if c) / (n_nodes - 1)
+            assert weighted == pytest.approx(r["snapshots"][g][0], abs=2e-4), (r["model"], r["tau"], g)
+            band = [v for k, (c, v) in enumerate(zip(counts, spec)) if 4 <= k <= 64 and c]
+            lo, hi = r["fig2_min_max_k4_64"][g]
+            assert lo == pytest.approx(min(band), abs=1.01e-4) and hi == pytest.approx(max(band), abs=1.01e-4)
