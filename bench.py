@@ -492,6 +492,7 @@ def summarize_valu(out_dir, storage, dims=(512, 512, 512)):
         acc.setdefault(short, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     path = os.path.join(ROOT, "profiles", f"step_{storage}_512_valu.txt")
     mean = lambda v: sum(v) / len(v) if v else 0.0
+    trace_ms = trace_kernel_ms(storage)
     with open(path, "w") as fh:
         fh.write(f"# VALU and SALU instructions of the step kernels, 512^3 {storage.upper()} bench workload "
                  "(4 timed + 2 warm-up steps)\n")
@@ -499,13 +500,37 @@ def summarize_valu(out_dir, storage, dims=(512, 512, 512)):
         fh.write(f"# kernel_source_hash = {kernel_hash()}\n")
         fh.write(f"# issue ms: VALU wave instructions x {FMA_CYCLES_PER_WAVE_INSTR:.2f} cycles / "
                  f"({SIMDS} SIMDs x {CLOCK_HZ / 1e9:.1f} GHz)\n")
-        fh.write("kernel | dispatches | VALU instructions per node | SALU instructions per node | issue ms\n")
+        fh.write(f"# VALU issue %: issue ms / the kernel's mean duration in "
+                 f"profiles/step_{storage}_512_kernel_trace.txt (same kernel source), the share of the\n"
+                 "# kernel's time the SIMDs need to issue its VALU instructions at the plain FP32 rate\n")
+        fh.write("kernel | dispatches | VALU instructions per node | SALU instructions per node | issue ms | "
+                 "kernel ms | VALU issue %\n")
         for k, c in sorted(acc.items()):
             valu, salu = c.get("SQ_INSTS_VALU", []), c.get("SQ_INSTS_SALU", [])
             issue_ms = mean(valu) * FMA_CYCLES_PER_WAVE_INSTR / (SIMDS * CLOCK_HZ) * 1e3
+            kms = trace_ms.get(k)
+            share = f"{kms:.3f} | {100.0 * issue_ms / kms:.1f}" if kms else "- | -"
             fh.write(f"{k} | {len(valu)} | {mean(valu) * 64 / n:.0f} | {mean(salu) * 64 / n:.0f} | "
-                     f"{issue_ms:.3f}\n")
+                     f"{issue_ms:.3f} | {share}\n")
     return path
+
+
+def trace_kernel_ms(storage):
+    """{short kernel name: mean duration in ms} from the committed kernel trace
+    summary of a storage type, or {} when it is missing or was taken on
+    another kernel source."""
+    path = os.path.join(ROOT, "profiles", f"step_{storage}_512_kernel_trace.txt")
+    if not os.path.exists(path):
+        return {}
+    out, same_source = {}, False
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# kernel_source_hash"):
+                same_source = line.split("=")[1].strip() == kernel_hash()
+            m = re.search(r"(step_\w*kernel<[^>]*>)\S* \| \d+ \| (\d+)", line)
+            if m and not line.startswith("#"):
+                out[m.group(1)] = float(m.group(2)) * 1e-6
+    return out if same_source else {}
 
 
 PROFILE_CMDS = {

@@ -83,13 +83,19 @@ def test_valu_summary(tmp_path, fake_root):
             rows.append(dict(Kernel_Name=name, Counter_Name="SQ_INSTS_SALU", Counter_Value=salu * n / 64))
     rows.append(dict(Kernel_Name=COPY, Counter_Name="SQ_INSTS_VALU", Counter_Value=1.0))
     write_csv(str(out / "prof_valu_f32" / "valu_counter_collection.csv"), ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+    # kernel durations come from the trace summary of the same kernel source
+    (fake_root / "profiles" / "step_f32_512_kernel_trace.txt").write_text(
+        "# command: ...\n# kernel_source_hash = 0123456789abcdef\nName | Calls | AverageNs | MinNs | MaxNs\n"
+        f"{EVEN} | 35 | 4000 | 3900 | 4100\n")
     path = bench.summarize_valu(str(out), "f32", dims=dims)
     text = open(path).read()
     # issue time: 711 n / 64 wave instructions x 2.63 cycles / (1024 SIMDs x 2.4 GHz)
     issue = 711 * n / 64 * bench.FMA_CYCLES_PER_WAVE_INSTR / (1024 * 2.4e9) * 1e3
-    assert f"step_wave_kernel<0, 7, true> | 3 | 711 | 10 | {issue:.3f}" in text
+    assert f"step_wave_kernel<0, 7, true> | 3 | 711 | 10 | {issue:.3f} | 0.004 | {100 * issue / 0.004:.1f}" in text
     assert "step_row_kernel<0, 7, true, false, true> | 3 | 833 | 20 |" in text
     assert "step_kernel<0, false, 7, true, true> | 3 | 763 | 30 |" in text
+    # no duration for a kernel the trace lacks
+    assert any(l.startswith("step_row_kernel") and l.endswith("| - | -") for l in text.splitlines())
     assert "copy_kernel" not in text
 
 
