@@ -129,3 +129,18 @@ def test_philox_is_the_published_round_bit_for_bit(ora, rounds):
         for r in reversed(range(rounds)):
             y = undo_round(y, (key[0] + r * PHILOX_W0) & MASK32, (key[1] + r * PHILOX_W1) & MASK32)
         assert y == ctr
+
+
+def test_weyl_increments_have_their_closed_forms():
+    """The two key increments of the round are the fractional parts of the
+    golden ratio, (sqrt(5) - 1) / 2, and of sqrt(3) - 1, in units of 2^-32
+    (rounded down), as the generator's authors define them.  Exact integer
+    square roots, so the check does not depend on floating point.  (The two
+    multipliers were found by a search and have no closed form; the inversion
+    test above fixes how they are used.)"""
+    import math
+    two32 = 1 << 32
+    # floor(2^32 (sqrt 5 - 1) / 2) = floor((sqrt(5 2^64) - 2^32) / 2)
+    assert (math.isqrt(5 * two32 * two32) - two32) // 2 == PHILOX_W0
+    # floor(2^32 (sqrt 3 - 1)) = floor(sqrt(3 2^64)) - 2^32
+    assert math.isqrt(3 * two32 * two32) - two32 == PHILOX_W1
