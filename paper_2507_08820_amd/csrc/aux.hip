@@ -30,10 +30,13 @@ __device__ __forceinline__ NodeXYZ coords(uint64_t n, uint32_t nx, uint32_t ny) 
   return c;
 }
 
-// Element index of slot A[plane][(x, y, z)] in the x-row blocked layout.
+// Element index of slot A[plane][(x, y, z)] in the x-row blocked layout, its
+// row blocks in By x Bz bricks (kernels.hpp; By = Bz = 1: plain layout).
 __device__ __forceinline__ uint64_t element_index(int plane, uint32_t x, uint32_t y, uint32_t z,
                                                   const GatherArgs& g) {
-  return z * g.plane_pitch + y * g.row_pitch + static_cast<uint64_t>(plane) * g.pop_pitch + x;
+  const uint64_t yo = (y >> g.by_log) * g.ybrick_pitch + (y & ((1u << g.by_log) - 1u)) * g.row_pitch;
+  const uint64_t zo = (z >> g.bz_log) * g.plane_pitch + (z & ((1u << g.bz_log) - 1u)) * g.zin_pitch;
+  return zo + yo + static_cast<uint64_t>(plane) * g.pop_pitch + x;
 }
 
 // Element index of the slot holding f_i(x) at the given parity.

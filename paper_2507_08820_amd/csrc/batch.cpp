@@ -44,7 +44,7 @@ BatchLayout batch_layout(int32_t n, const rflbm_params* p) {
   uint64_t tiles128 = 0;
   for (int32_t r = 0; r < n; ++r) {
     B.region_off.push_back(off);
-    off += align_up(layout_for(p[r]).total, kAlign);
+    off += align_up(layout_for(p[r], false).total, kAlign);
     tiles128 += (node_count(p[r]) + 127) / 128;
   }
   B.max_tiles = static_cast<uint32_t>(tiles128);
@@ -341,7 +341,7 @@ rflbm_status rflbm_batch_create(int32_t n, const rflbm_params* p, void* dev_buf,
       rflbm_batch_destroy(b);
       return fail(RFLBM_ENOMEM, "host allocation failed");
     }
-    lattice_init(v, p[r], b->buf + B.region_off[r], b->stream);
+    lattice_init(v, p[r], b->buf + B.region_off[r], b->stream, false);  // plain layout
     v->is_view = true;
     b->views.push_back(v);
     if (lattice_clear(v) != hipSuccess) {

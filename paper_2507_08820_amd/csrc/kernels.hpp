@@ -2,12 +2,17 @@
 // kernels of the fluctuating lattice Boltzmann step (arXiv:2507.08820, Sec. II).
 //
 // Population storage ("AA" in-place streaming, one lattice copy), blocked by
-// x-rows: the 27 population rows of row r = y + ny z are contiguous, element
-// (i, x) of row (y, z) at index z P + y R + i Q + x, with population-row pitch
-// Q >= nx, row pitch R >= 27 Q and plane pitch P >= ny R (padding, if any, at
-// the end of each population row, row block and plane).  A[i][n] below names
-// that slot of node n = x + nx (y + ny z).  Each slot holds the deviation f - w_i rho0
-// (divided by sigma_class(i) for 16-bit storage).
+// x-rows: the 27 population rows of the x-row (y, z) are contiguous (an x-row
+// block), element (i, x) of it at offset i Q + x, population-row pitch Q >= nx.
+// The row blocks themselves are stored in bricks of By x Bz rows (y fastest
+// inside a brick), the bricks y-major within a brick row of Bz planes:
+//   block(y, z) = Y(y) + Z(z),
+//   Y(y) = (y / By) Yb + (y mod By) R,   Z(z) = (z / Bz) P + (z mod Bz) Zi,
+// with R >= 27 Q, Zi = By R, Yb = By Bz R and P >= (ny / By) Yb (By, Bz
+// powers of two dividing ny and nz; By = Bz = 1 is the plain layout, rows
+// y-major within planes, P the plane pitch).  A[i][n] below names slot (i, x)
+// of the row block of node n = x + nx (y + ny z).  Each slot holds the
+// deviation f - w_i rho0 (divided by sigma_class(i) for 16-bit storage).
 //   After an even number t of steps: f_i(x, t) = A[i][x].
 //   After an odd number t of steps:  f_i(x, t) = A[26 - i][x - c_i].
 // An even step reads A[i][x] and writes f*_i(x) to A[26 - i][x]; an odd step
@@ -33,9 +38,12 @@ constexpr int kAccDoubles = 32;  // device accumulator block: 23 sums, samples, 
 struct StepArgs {
   void* pop;             // populations, x-row blocked
   uint32_t nx, ny, nz;   // box
-  uint32_t pop_pitch;    // bytes from population row i to row i + 1 of one x-row block
-  uint32_t row_pitch;    // bytes from one x-row block (27 population rows) to the next in y
-  uint64_t plane_pitch;  // bytes from one z plane of row blocks to the next
+  uint32_t pop_pitch;    // bytes from population row i to row i + 1 of one x-row block (Q)
+  uint32_t row_pitch;    // bytes from one x-row block to the next in y inside a brick (R)
+  uint32_t ybrick_pitch; // bytes from one brick to the next in y (Yb; R when By = 1)
+  uint32_t zin_pitch;    // bytes from one x-row block to the next in z inside a brick (Zi)
+  uint32_t by_log, bz_log;  // log2 of the brick shape By x Bz (0, 0: plain layout)
+  uint64_t plane_pitch;  // bytes from one brick row (Bz z planes) to the next (P)
   uint32_t tiles_x;      // tiles along x (tile = blockDim.x x blockDim.y nodes of one z plane)
   uint32_t tiles_y;      // tiles along y
   uint32_t ntiles;       // tiles_x * tiles_y * nz
@@ -43,6 +51,7 @@ struct StepArgs {
   FastDiv div_tiles_x;   // division by tiles_x (when tiles_x >= 2)
   FastDiv div_tiles_y;   // division by tiles_y (when tiles_y >= 2)
   FastDiv div_ny;        // division by ny
+  FastDiv div_nyb;       // division by ny / By (bricks along y)
   FastDiv div_segs;      // division by nx / 64 (when nx / 64 >= 2)
   uint32_t step;         // t mod 2^32 (Philox counter word 1)
   uint32_t key0, key1;   // Philox key
@@ -65,6 +74,19 @@ struct StepArgs {
   int* flag;             // set to 1 on rho <= 0 or non-finite rho, j
   double* partials;      // statistics partials, column-major [kNumStats][gridDim.x]
 };
+
+// Byte offsets of the row block of (y, z): the y part Y(y) and the z part Z(z)
+// of the brick layout above.
+// (A: StepArgs in any address space.)
+template <class A>
+__host__ __device__ __forceinline__ uint32_t row_off_y(uint32_t y, const A& a) {
+  return (y >> a.by_log) * a.ybrick_pitch + (y & ((1u << a.by_log) - 1u)) * a.row_pitch;
+}
+template <class A>
+__host__ __device__ __forceinline__ uint64_t row_off_z(uint32_t z, const A& a) {
+  return static_cast<uint64_t>(z >> a.bz_log) * a.plane_pitch +
+         static_cast<uint64_t>((z & ((1u << a.bz_log) - 1u)) * a.zin_pitch);
+}
 
 // One replica of a batch: its lattice arguments plus what the batched kernel
 // needs to turn a tile-local flattened node index into (x, y, z).
@@ -133,9 +155,12 @@ hipError_t launch_stats_reduce(const double* partials, uint32_t grid, double* sc
 struct GatherArgs {
   const void* pop;
   uint32_t nx, ny, nz;
-  uint64_t pop_pitch;     // elements from population row i to row i + 1 of a block
-  uint64_t row_pitch;     // elements from one x-row block to the next in y
-  uint64_t plane_pitch;   // elements from one z plane to the next
+  uint64_t pop_pitch;     // elements from population row i to row i + 1 of a block (Q)
+  uint64_t row_pitch;     // elements from one x-row block to the next in y inside a brick (R)
+  uint64_t ybrick_pitch;  // elements from one brick to the next in y (Yb)
+  uint64_t zin_pitch;     // elements from one x-row block to the next in z inside a brick (Zi)
+  uint64_t plane_pitch;   // elements from one brick row (Bz z planes) to the next (P)
+  uint32_t by_log, bz_log;  // brick shape, as in StepArgs
   uint32_t odd;           // parity of the current step count
   double rho0;
   float sigma[4];

@@ -16,8 +16,11 @@ namespace rflbm {
 // flag, the FP64 accumulators, the statistics partials and reduction scratch.
 struct Layout {
   uint32_t pop_pitch;    // bytes between the population rows of one x-row block
-  uint32_t row_pitch;    // bytes between x-row blocks (27 population rows) in y
-  uint64_t plane_pitch;  // bytes between z planes
+  uint32_t row_pitch;    // bytes between x-row blocks (27 population rows) in y inside a brick
+  uint32_t ybrick_pitch; // bytes between bricks in y
+  uint32_t zin_pitch;    // bytes between x-row blocks in z inside a brick
+  uint32_t by_log, bz_log;  // brick shape (kernels.hpp); 0, 0: plain layout
+  uint64_t plane_pitch;  // bytes between brick rows (between z planes when bz_log = 0)
   size_t pop_bytes;
   size_t flag_off, acc_off, partial_off, scratch_off, total;
   uint32_t grid_max;
@@ -42,10 +45,12 @@ static_assert(RFLBM_POP_PAD % 128 == 0 && RFLBM_ROW_PAD % 256 == 0 && RFLBM_PLAN
 size_t align_up(size_t v, size_t a);
 uint64_t node_count(const rflbm_params& p);
 std::string validate(const rflbm_params* p);
-Layout layout_for(const rflbm_params& p);
+// Layout of a lattice's buffer; `bricks`: row blocks in bricks where the box
+// allows (single boxes), else the plain layout (batch replicas).
+Layout layout_for(const rflbm_params& p, bool bricks = true);
 uint64_t pop_pitch_of(const rflbm_params& p);    // bytes between population rows
 uint64_t row_pitch_of(const rflbm_params& p);    // bytes between x-row blocks
-uint64_t plane_pitch_of(const rflbm_params& p);  // bytes between z planes
+uint64_t plane_pitch_of(const rflbm_params& p);  // bytes between z planes (plain layout)
 rflbm_status fail(rflbm_status st, const std::string& msg);
 
 }  // namespace rflbm
@@ -85,7 +90,8 @@ StepArgs step_args(const rflbm_lattice* L);
 // at step count t (the parity of t selects the AA layout).
 GatherArgs gather_args(const rflbm_lattice* L, const rflbm_params& p, int64_t t);
 // Sets up a lattice object on an existing buffer (no allocation, no kernels).
-void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStream_t s);
+// `bricks` as for layout_for.
+void lattice_init(rflbm_lattice* L, const rflbm_params& p, uint8_t* buf, hipStream_t s, bool bricks = true);
 // Zeroes the populations (rest state), flag and accumulators of L.
 hipError_t lattice_clear(rflbm_lattice* L);
 // Releases what the library allocated for L (S(k) scratch, owned buffer).

@@ -85,6 +85,20 @@ __device__ __forceinline__ constexpr bool store_nt(bool x_aligned) {
 #define RFLBM_ROW_GROUP_Z 8
 #endif
 
+// x-row r = 0 .. ny nz - 1 of a visiting order -> (y, z).  With the row blocks
+// in bricks, the bricks in memory order and y fastest inside each (a
+// sequential walk of the populations; the odd step's 9 source and 9
+// destination row blocks of a row lie in the brick of the row or its
+// neighbours); otherwise rows in plane order.
+__device__ __forceinline__ void brick_row(uint32_t r, const StepArgs& a, uint32_t& y, uint32_t& z) {
+  const uint32_t inner = r & ((1u << (a.by_log + a.bz_log)) - 1u);
+  const uint32_t brick = r >> (a.by_log + a.bz_log);
+  const uint32_t zb = div_by(brick, a.ny >> a.by_log, a.div_nyb);
+  const uint32_t yb = brick - zb * (a.ny >> a.by_log);
+  y = (yb << a.by_log) + (inner & ((1u << a.by_log) - 1u));
+  z = (zb << a.bz_log) + (inner >> a.by_log);
+}
+
 // Whole-row odd step: whole aligned cache lines that no other wave touches,
 // like those of the even step.
 #ifndef RFLBM_ROW_LOAD_NT
@@ -208,17 +222,23 @@ __device__ __forceinline__ void row_shift(uint32_t (&v)[kQ], uint32_t (*edge)[kM
   }
 }
 
-// One box: a block covers bx x by nodes of one z plane (blockDim = (bx, by)).
+// One box: a block covers bx x by nodes of one z plane (blockDim = (bx, by));
+// blocks of one row (by = 1) take the rows in memory order, others plane by plane.
 template <int S, bool ODD, int ROUNDS, bool STATS, bool GEQ>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
   uint32_t tile = blockIdx.x;
   if (a.xcd_remap) tile = (tile & 7u) * (gridDim.x >> 3) + (tile >> 3);
   const uint32_t rest = div_by(tile, a.tiles_x, a.div_tiles_x);
   const uint32_t tx = tile - rest * a.tiles_x;
-  const uint32_t z = div_by(rest, a.tiles_y, a.div_tiles_y);
-  const uint32_t ty = rest - z * a.tiles_y;
+  uint32_t y, z;
+  if (blockDim.y == 1) {
+    // tiles of one row: rows in memory order (brick by brick)
+    brick_row(rest, a, y, z);
+  } else {
+    z = div_by(rest, a.tiles_y, a.div_tiles_y);
+    y = (rest - z * a.tiles_y) * blockDim.y + threadIdx.y;
+  }
   const uint32_t x = tx * blockDim.x + threadIdx.x;
-  const uint32_t y = ty * blockDim.y + threadIdx.y;
   const uint32_t tid = threadIdx.x + blockDim.x * threadIdx.y;
   const bool active = tile < a.ntiles && x < a.nx && y < a.ny;
 
@@ -230,6 +250,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     [[maybe_unused]] float (*stat_wave)[kMaxRowWaves] = nullptr;
     constexpr bool SMALL_BOX = false;
     constexpr bool BUFFER_ACCESS = true;
+    constexpr bool BRICKS = true;
     constexpr bool ROW_SHIFT = false;
     constexpr bool GHOST_EQ = GEQ;
     [[maybe_unused]] uint32_t (*row_edge_in)[kMaxRowWaves] = nullptr;
@@ -262,10 +283,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 }
 
 // Even step without statistics in one-wave blocks: block b covers the 64
-// nodes x = 64 (b mod (nx / 64)) + lane of one x-row (nx a multiple of 64).
+// nodes x = 64 (b mod (nx / 64)) + lane of x-row b / (nx / 64) of the memory
+// order (brick_row; nx a multiple of 64).
 template <int S, int ROUNDS, bool GEQ>
 __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
   constexpr bool ODD = false, STATS = false, SMALL_BOX = false, ROW_SHIFT = false, BUFFER_ACCESS = true;
+  constexpr bool BRICKS = true;
   constexpr bool GHOST_EQ = GEQ, STATS_WAVE = false;
   [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
   [[maybe_unused]] float (*stat_wave)[kMaxRowWaves] = nullptr;
@@ -278,14 +301,15 @@ __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
   const uint32_t row = div_by(seg, per_row, a.div_segs);
   if (row >= a.ny * a.nz) return;  // the whole block: rounding of the grid to 8
   const uint32_t x = (seg - row * per_row) * 64 + threadIdx.x;
-  const uint32_t z = div_by(row, a.ny, a.div_ny);
-  const uint32_t y = row - z * a.ny;
+  uint32_t y, z;
+  brick_row(row, a, y, z);
   const uint32_t step = a.step;
 #include "node_body.inc"
 }
 
-// A step of one box in whole-row blocks: block b covers the x-row (y, z) of
-// row index y + ny z (blockDim.x = nx, a multiple of 64 up to 1024).  On odd
+// A step of one box in whole-row blocks: block b covers one x-row (blockDim.x
+// = nx, a multiple of 64 up to 1024), rows in memory order (brick_row) or, in
+// the plain layout, grouped on odd steps.  On odd
 // steps the +-1 shifts in x stay inside the block and every load and store is
 // a whole aligned cache line (see row_shift).  With STATS, each wave sums its
 // nodes' statistics, and the block adds its waves' sums in FP64 (fixed order)
@@ -293,7 +317,7 @@ __global__ void __launch_bounds__(64) step_wave_kernel(const StepArgs a) {
 // kernel only for statistics (one partial per row instead of one per wave).
 template <int S, int ROUNDS, bool GEQ, bool STATS, bool ODD>
 __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepArgs a) {
-  constexpr bool SMALL_BOX = false, ROW_SHIFT = ODD, BUFFER_ACCESS = true;
+  constexpr bool SMALL_BOX = false, ROW_SHIFT = ODD, BUFFER_ACCESS = true, BRICKS = true;
   constexpr bool GHOST_EQ = GEQ, STATS_WAVE = true;
   [[maybe_unused]] float (*stat_lds)[kBlock] = nullptr;
   [[maybe_unused]] const uint32_t tid = 0;
@@ -309,12 +333,15 @@ __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepA
     return;
   }
   const uint32_t x = threadIdx.x;
-#if RFLBM_ROW_GROUP_Y * RFLBM_ROW_GROUP_Z > 1
-  // odd steps: rows visited in groups of GY x GZ (y, z) so that the 9 row
-  // blocks a row reads from and writes to are in use at about the same time
-  constexpr uint32_t GY = ODD ? RFLBM_ROW_GROUP_Y : 1, GZ = ODD ? RFLBM_ROW_GROUP_Z : 1;
   uint32_t y, z;
-  {
+  if (a.by_log + a.bz_log > 0) {
+    brick_row(row, a, y, z);
+  } else {
+#if RFLBM_ROW_GROUP_Y * RFLBM_ROW_GROUP_Z > 1
+    // plain layout, odd steps: rows visited in groups of GY x GZ (y, z) so
+    // that the 9 row blocks a row reads from and writes to are in use at
+    // about the same time
+    constexpr uint32_t GY = ODD ? RFLBM_ROW_GROUP_Y : 1, GZ = ODD ? RFLBM_ROW_GROUP_Z : 1;
     const uint32_t per_zgroup = a.ny * GZ;
     const uint32_t zg = row / per_zgroup;
     const uint32_t r2 = row - zg * per_zgroup;
@@ -324,11 +351,11 @@ __global__ void __launch_bounds__(kMaxRowWaves * 64) step_row_kernel(const StepA
     const uint32_t gyw = min(GY, a.ny - yg * GY);
     y = yg * GY + r3 % gyw;
     z = zg * GZ + r3 / gyw;
-  }
 #else
-  const uint32_t y = row % a.ny;
-  const uint32_t z = row / a.ny;
+    y = row % a.ny;
+    z = row / a.ny;
 #endif
+  }
   const uint32_t step = a.step;
 #include "node_body.inc"
   if constexpr (STATS) {
@@ -355,6 +382,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchArgs b) {
   constexpr bool STATS_WAVE = false;
   [[maybe_unused]] float (*stat_wave)[kMaxRowWaves] = nullptr;
   constexpr bool SMALL_BOX = true;  // every replica region is below 4 GiB
+  constexpr bool BRICKS = false;    // replicas keep the plain layout
   // buffer instructions measured faster for 16-bit storage, global ones for
   // FP32 (64 replicas of 32^3..96^3: 38.9 vs 36.6 and 24.6 vs 25.9 GLUPS)
   constexpr bool BUFFER_ACCESS = S != kF32;

@@ -83,6 +83,11 @@ CASES = {
                                         tau_ghost=list(np.linspace(0.55, 1.9, 17)), seed=20)),
     "rows_rec_128x5x3": ((128, 5, 3), dict(kT=1e-4, tau=0.6, model="rec", tau_ghost=0.8, seed=21)),
     "rec_kT0_33x7x6": ((33, 7, 6), dict(kT=0.0, tau=0.9, model="rec", tau_ghost=1.5)),
+    # row blocks stored in bricks of 2 x 16 and 2 x 8 (y, z), several bricks
+    # along both axes, on the row-aligned kernels (shorter boxes take smaller
+    # bricks: 16^3 2 x 16, 300x3x4 1 x 4, 12x20x9 2 x 1, ...)
+    "bricks_64x6x32": ((64, 6, 32), dict(kT=1e-4, tau=0.6, seed=22)),
+    "bricks_kT0_128x4x24": ((128, 4, 24), dict(kT=0.0, tau=0.7)),
 }
 
 
