@@ -49,14 +49,19 @@
  *     permutations of those indices), the original term included;
  *   - the random numbers: Philox4x32-R (Salmon, Moraes, Dror and Shaw, SC'11,
  *     "Parallel random numbers: as easy as 1, 2, 3") with key (seed low word,
- *     seed high word) and counter (node, step, call j = 0..5, stream id); word
- *     w of call j is uniform q = 4j + w, made of the word's top 23 bits
- *     b = word >> 9: a radius uniform (q even) U_q = 1 - b 2^-23 in
- *     [2^-23, 1], an angle uniform (q odd) U_q = b 2^-23 in [0, 1), both
- *     held exactly in single precision; the Box-Muller transform of pairs
- *     (U_2p, U_2p+1) gives z_2p = R cos(theta), z_2p+1 = R sin(theta),
- *     R = sqrt(-2 ln U_2p), theta = 2 pi U_2p+1; mode k (4..26) receives
- *     r_k = z_(k-4); z_23 is unused.
+ *     seed high word) and counter (node, step, call j = 0..3, stream id).
+ *     The four words w0..w3 of call j give three Box-Muller pairs p = 3j + m:
+ *     radius uniforms from the top 23 bits b = w_m >> 9 of w0, w1, w2,
+ *     U_2p = 1 - b 2^-23 in [2^-23, 1]; angle uniforms from 16 bits a,
+ *     U_2p+1 = a 2^-16 in [0, 1), with a = w3 >> 16 (m = 0), w3 & 0xFFFF
+ *     (m = 1) and (w0 & 0xFF) 2^8 + (w1 & 0xFF) (m = 2), bits the radii do
+ *     not use; all held exactly in single precision.  The Box-Muller
+ *     transform of (U_2p, U_2p+1) gives z_2p = R cos(theta), z_2p+1 =
+ *     R sin(theta), R = sqrt(-2 ln U_2p), theta = 2 pi U_2p+1; mode k (4..26)
+ *     receives r_k = z_(k-4); z_23 is unused.  (16 angle bits are plenty:
+ *     the variance of R cos(theta) over a grid of 2^16 angles is exact; the
+ *     radius keeps 23 bits because its smallest uniform sets the tail, here
+ *     at 5.65 standard deviations.)
  *
  * Pins.  The Philox bit stream is pinned to the published definition of the
  * round by inversion: the tests undo R rounds of that definition (its odd
@@ -239,12 +244,16 @@ void ora_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t round
   out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* Uniform number w of a Philox call from its word: the top 23 bits
- * b = word >> 9, as 1 - b 2^-23 in [2^-23, 1] for a radius (w even, never 0,
- * so the logarithm is finite) or b 2^-23 in [0, 1) for an angle (w odd). */
-static double uniform_of_word(uint32_t word, int w) {
-  const double b = (double)(word >> 9) / 8388608.0;
-  return (w % 2 == 0) ? 1.0 - b : b;
+/* Uniforms 6j .. 6j + 5 (three radius-angle pairs) from the four words of
+ * Philox call j, as laid out in the header: radius uniforms 1 - b 2^-23 from
+ * the top 23 bits of words 0, 1, 2 (never 0, so the logarithm is finite),
+ * angle uniforms a 2^-16 from 16 bits the radii leave unused. */
+static void uniforms_of_call(const uint32_t w[4], double u[6]) {
+  const uint32_t angle_bits[3] = {w[3] >> 16, w[3] & 0xFFFFu, ((w[0] & 0xFFu) << 8) | (w[1] & 0xFFu)};
+  for (int m = 0; m < 3; ++m) {
+    u[2 * m] = 1.0 - (double)(w[m] >> 9) / 8388608.0;
+    u[2 * m + 1] = (double)angle_bits[m] / 65536.0;
+  }
 }
 
 /* The 24 uniforms of one (node, step, stream) and their 24 Box-Muller normals.
@@ -252,11 +261,11 @@ static double uniform_of_word(uint32_t word, int w) {
 void ora_uniforms(uint64_t seed, uint32_t stream_id, uint32_t rounds, uint32_t node, uint32_t step,
                   double u[24]) {
   const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
-  for (uint32_t j = 0; j < 6; ++j) {
+  for (uint32_t j = 0; j < 4; ++j) {
     const uint32_t ctr[4] = {node, step, j, stream_id};
     uint32_t words[4];
     ora_philox4x32(ctr, key, rounds, words);
-    for (int w = 0; w < 4; ++w) u[4 * j + w] = uniform_of_word(words[w], w);
+    uniforms_of_call(words, u + 6 * j);
   }
 }
 
@@ -503,8 +512,8 @@ int ora_run(const ora_params* p, int32_t nx, int32_t ny, int32_t nz, uint32_t st
  * mu = rho0 kT / c_s^2, the stationary covariance mu w_i delta_ij that the
  * fluctuation-dissipation balance of Eq. fluct_phi sustains in the linear
  * regime.  xi_i is the i-th normal of the node's Box-Muller stream drawn at the
- * reserved step word 0xFFFFFFFF with calls j = 0..6 (28 normals, 27 used):
- * word w of call j gives uniform 4j + w as in ora_uniforms. */
+ * reserved step word 0xFFFFFFFF with calls j = 0..4 (30 normals, 27 used):
+ * call j gives uniforms 6j .. 6j + 5 as in ora_uniforms. */
 int ora_init_thermal(const ora_params* p, int32_t nx, int32_t ny, int32_t nz, const double* rho,
                      const double* u, double* f) {
   build_tables();
@@ -513,16 +522,16 @@ int ora_init_thermal(const ora_params* p, int32_t nx, int32_t ny, int32_t nz, co
   const double mu = p->rho0 * p->kT / CS2;
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < N; ++n) {
-    double fe[NPOP], uni[28], z[28];
+    double fe[NPOP], uni[30], z[30];
     const double un[3] = {u ? u[n] : 0.0, u ? u[N + n] : 0.0, u ? u[2 * N + n] : 0.0};
     ora_equilibrium(rho ? rho[n] : p->rho0, un, fe);
-    for (uint32_t j = 0; j < 7; ++j) {
+    for (uint32_t j = 0; j < 5; ++j) {
       const uint32_t ctr[4] = {(uint32_t)n, 0xFFFFFFFFu, j, p->stream_id};
       uint32_t words[4];
       ora_philox4x32(ctr, key, p->rounds, words);
-      for (int w = 0; w < 4; ++w) uni[4 * j + w] = uniform_of_word(words[w], w);
+      uniforms_of_call(words, uni + 6 * j);
     }
-    for (int q = 0; q < 14; ++q) {
+    for (int q = 0; q < 15; ++q) {
       const double radius = sqrt(-2.0 * log(uni[2 * q]));
       const double theta = 2.0 * 3.14159265358979323846 * uni[2 * q + 1];
       z[2 * q] = radius * cos(theta);

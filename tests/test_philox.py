@@ -6,7 +6,9 @@ Box-Muller.  The bit stream is pinned
 to the published definition of the round without any known-answer vectors:
 undoing R rounds of that definition (its multipliers are odd, hence invertible
 mod 2^32) must give back the counter of every draw.  Also checked: the uniforms
-lie on the 23-bit grids and are uniform, the normals have the moments and
+take the documented bits of the Philox words (three radius-angle pairs per
+call), lie on their 23-bit (radius) and 16-bit (angle) grids and are uniform,
+the normals have the moments and
 distribution of N(0, 1), the Box-Muller pairing follows the documented counter
 layout, and draws at neighbouring counters (node, step, call) are uncorrelated.
 """
@@ -19,22 +21,53 @@ def draw(ora, nodes, step=0, seed=1, stream=0, rounds=7):
     return np.array([ora.normals(seed, stream, rounds, n, step) for n in nodes])
 
 
-def test_uniforms_on_23_bit_grid(ora):
+def test_uniforms_on_their_grids(ora):
     """Radius uniforms (even positions) lie on the grid 1 - b 2^-23 in
-    [2^-23, 1] (never 0, so the logarithm is finite), angle uniforms (odd
-    positions) on b 2^-23 in [0, 1), b a 23-bit integer; every value is exact
-    in single precision, and both sets are uniform."""
-    u = np.array([ora.uniforms(7, 0, 10, n, 3) for n in range(2000)])
+    [2^-23, 1] (never 0, so the logarithm is finite), b a 23-bit integer;
+    angle uniforms (odd positions) on a 2^-16 in [0, 1), a a 16-bit integer;
+    every value is exact in single precision, and both sets are uniform."""
+    u = np.array([ora.uniforms(7, 0, 10, n, 3) for n in range(3000)])
     rad, ang = u[:, 0::2].ravel(), u[:, 1::2].ravel()
-    for b in ((1.0 - rad) * 2 ** 23, ang * 2 ** 23):
+    for b, bits in (((1.0 - rad) * 2 ** 23, 23), (ang * 2 ** 16, 16)):
         np.testing.assert_array_equal(b, np.round(b))
-        assert b.min() >= 0 and b.max() <= 2 ** 23 - 1
+        assert b.min() >= 0 and b.max() <= 2 ** bits - 1
     assert rad.min() >= 2.0 ** -23 and rad.max() <= 1 and ang.min() >= 0 and ang.max() < 1
     np.testing.assert_array_equal(u.astype(np.float32).astype(np.float64), u)
     for x in (rad, ang):
         assert stats.kstest(x, "uniform").pvalue > 1e-4
-    # the draws spread over the whole range
+    # the draws spread over the whole range, and every angle position does
     assert (1.0 - rad).max() > 0.999 and ang.max() > 0.999 and ang.min() < 1e-3
+    for m in range(3):
+        assert stats.kstest(u[:, 2 * m + 1::6].ravel(), "uniform").pvalue > 1e-4
+
+
+def test_uniforms_take_the_documented_bits(ora):
+    """Call j = 0..3 of the node's Philox stream gives pairs 3j .. 3j + 2: the
+    radii from the top 23 bits of words 0, 1, 2; the angles from the high and
+    the low half of word 3 and from the low bytes of words 0 and 1 (bits no
+    radius uses), so one call of 128 bits carries three pairs."""
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        seed = int(rng.integers(0, 1 << 63))
+        node, step, sid = (int(v) for v in rng.integers(0, 1 << 32, 3, dtype=np.uint64))
+        u = ora.uniforms(seed, sid, 7, node, step)
+        for j in range(4):
+            w = [int(v) for v in ora.philox4x32([node, step, j, sid], [seed & 0xFFFFFFFF, seed >> 32], 7)]
+            angle = [w[3] >> 16, w[3] & 0xFFFF, ((w[0] & 0xFF) << 8) | (w[1] & 0xFF)]
+            for m in range(3):
+                assert u[6 * j + 2 * m] == 1.0 - (w[m] >> 9) * 2.0 ** -23
+                assert u[6 * j + 2 * m + 1] == angle[m] * 2.0 ** -16
+
+
+def test_radius_and_angle_uniforms_independent(ora):
+    """The third angle shares its words with two radii (disjoint bits): no
+    correlation between any radius and any angle of a call."""
+    u = np.array([ora.uniforms(11, 2, 7, n, 8) for n in range(20000)])
+    for j in range(4):
+        for m in range(3):
+            for mm in range(3):
+                r = np.corrcoef(u[:, 6 * j + 2 * m], u[:, 6 * j + 2 * mm + 1])[0, 1]
+                assert abs(r) < 5 / np.sqrt(len(u))
 
 
 def test_box_muller_pairing(ora):
