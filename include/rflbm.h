@@ -26,11 +26,12 @@
  *     current step count t.
  *   Random numbers (r_k ~ N(0, 1) of Eq. fluct_phi; the paper leaves the
  *     generator open): Philox4x32 with key (seed low word, seed high word) and
- *     counter (n, t mod 2^32, j = 0..5, stream_id); word w of call j gives
- *     uniform 4 j + w from its top 23 bits b = word >> 9, 1 - b 2^-23 for the
- *     radius (w even) and b 2^-23 for the angle (w odd) of a Box-Muller pair;
- *     the pairs give normals z_q, and mode k (Table II order, 4..26) receives
- *     z_(k-4).  The trajectory is therefore a function of (params, initial
+ *     counter (n, t mod 2^32, j = 0..3, stream_id); the words w0..w3 of call
+ *     j carry Box-Muller pairs 3 j + m, m = 0..2: radius uniform 1 - b 2^-23
+ *     from the top 23 bits b = w_m >> 9, angle uniform a 2^-16 from
+ *     a = w3 >> 16, w3 & 0xFFFF and (w0 & 0xFF) 2^8 + (w1 & 0xFF) for
+ *     m = 0, 1, 2; pair p gives normals z_2p, z_2p+1, and mode k (Table II
+ *     order, 4..26) receives z_(k-4).  The trajectory is therefore a function of (params, initial
  *     state) only, on any device or host.
  *   Memory: "device" pointers are HIP device allocations (for instance torch
  *     tensors on the GPU); "host" pointers are ordinary memory.  Host arrays
@@ -149,7 +150,7 @@ rflbm_status rflbm_init_equilibrium(rflbm_lattice* lat, const double* rho, const
  * the stationary covariance of the fluctuating update in the linear regime
  * (Eq. fluct_phi), so that statistics need no equilibration transient.  xi_i
  * is normal i of the node's Philox/Box-Muller stream at the reserved step word
- * 0xFFFFFFFF (calls j = 0..6; 27 of 28 normals used), keyed like the step's
+ * 0xFFFFFFFF (calls j = 0..4; 27 of 30 normals used), keyed like the step's
  * noise.  Arguments as for rflbm_init_equilibrium. */
 rflbm_status rflbm_init_thermal(rflbm_lattice* lat, const double* rho, const double* u,
                                 int host_ptrs);

@@ -141,7 +141,7 @@ __global__ void init_eq_kernel(const GatherArgs g, const double* rho, const doub
 // Thermalised start: f_i = f^(0)_i(rho, u) + sqrt(rho0 kT w_i / cs2) xi_i, the
 // stationary covariance of the fluctuating update (Eq. fluct_phi) in the
 // linear regime.  xi_i is normal i of the node's Box-Muller stream at the
-// reserved step word 0xFFFFFFFF, Philox calls j = 0..6 (28 normals, 27 used);
+// reserved step word 0xFFFFFFFF, Philox calls j = 0..4 (30 normals, 27 used);
 // set-up code, so the transform runs in FP64.
 template <int S, int R>
 __global__ void init_thermal_kernel(const GatherArgs g, const double* rho, const double* u, uint32_t key0,
@@ -164,21 +164,22 @@ __global__ void init_thermal_kernel(const GatherArgs g, const double* rho, const
       fac[a][1] = (2.0 / 3.0) * (1.0 - 1.5 * uu);
       fac[a][2] = (1.0 / 6.0) * (1.0 + 3.0 * ua[a] + 3.0 * uu);
     }
-    double z[28];
+    double z[30];
 #pragma unroll
-    for (uint32_t j = 0; j < 7; ++j) {
+    for (uint32_t j = 0; j < 5; ++j) {
       const Word4 w = philox<R>(Word4{static_cast<uint32_t>(n), 0xFFFFFFFFu, j, sid}, key0, key1);
-      // radius uniforms 1 - b 2^-23, angle uniforms b 2^-23, b = word >> 9
-      const double u0 = 1.0 - static_cast<double>(w.w0 >> 9) * 0x1p-23;
-      const double u1 = static_cast<double>(w.w1 >> 9) * 0x1p-23;
-      const double u2 = 1.0 - static_cast<double>(w.w2 >> 9) * 0x1p-23;
-      const double u3 = static_cast<double>(w.w3 >> 9) * 0x1p-23;
-      const double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
+      // pair m: radius uniform 1 - (w_m >> 9) 2^-23, angle uniform a_m 2^-16
+      const uint32_t wr[3] = {w.w0, w.w1, w.w2};
+      const uint32_t am[3] = {w.w3 >> 16, w.w3 & 0xFFFFu, ((w.w0 & 0xFFu) << 8) | (w.w1 & 0xFFu)};
       const double two_pi = 6.283185307179586476925;
-      z[4 * j + 0] = ra * cos(two_pi * u1);
-      z[4 * j + 1] = ra * sin(two_pi * u1);
-      z[4 * j + 2] = rb * cos(two_pi * u3);
-      z[4 * j + 3] = rb * sin(two_pi * u3);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double ur = 1.0 - static_cast<double>(wr[m] >> 9) * 0x1p-23;
+        const double ua = static_cast<double>(am[m]) * 0x1p-16;
+        const double rad = sqrt(-2.0 * log(ur));
+        z[6 * j + 2 * m] = rad * cos(two_pi * ua);
+        z[6 * j + 2 * m + 1] = rad * sin(two_pi * ua);
+      }
     }
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
@@ -257,16 +258,22 @@ __global__ void rng_kernel(uint32_t key0, uint32_t key1, uint32_t sid, uint32_t 
   if (t >= count) return;
   const uint32_t node = node0 + t;
 #pragma unroll
-  for (uint32_t j = 0; j < 6; ++j) {
+  for (uint32_t j = 0; j < 4; ++j) {
     const Word4 w = philox<R>(Word4{node, step, j, sid}, key0, key1);
-    const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
-    float r[4];
-    box_muller(w.w0, w.w1, r[0], r[1]);
-    box_muller(w.w2, w.w3, r[2], r[3]);
+    float r[6], uu[6];
+    box_muller<0>(w, r[0], r[1]);
+    box_muller<1>(w, r[2], r[3]);
+    box_muller<2>(w, r[4], r[5]);
+    uu[0] = radius_uniform(w.w0);
+    uu[1] = angle_uniform<0>(w);
+    uu[2] = radius_uniform(w.w1);
+    uu[3] = angle_uniform<1>(w);
+    uu[4] = radius_uniform(w.w2);
+    uu[5] = angle_uniform<2>(w);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      u[static_cast<uint64_t>(t) * 24 + 4 * j + q] = (q % 2 == 0) ? radius_uniform(ws[q]) : angle_uniform(ws[q]);
-      z[static_cast<uint64_t>(t) * 24 + 4 * j + q] = r[q];
+    for (int q = 0; q < 6; ++q) {
+      u[static_cast<uint64_t>(t) * 24 + 6 * j + q] = uu[q];
+      z[static_cast<uint64_t>(t) * 24 + 6 * j + q] = r[q];
     }
   }
 }

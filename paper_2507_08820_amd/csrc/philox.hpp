@@ -10,15 +10,17 @@
 // words advance by Weyl increments between rounds.
 //
 // Use in the step kernel: key = (seed low, seed high), counter =
-// (node, step, call j, stream id), j = 0..5.  Words (0, 1) and (2, 3) of a call
-// are Box-Muller pairs, each word giving a uniform from its top 23 bits
-// b = w >> 9: the radius word U0 = 1 - b 2^-23 in [2^-23, 1], the angle word
-// U1 = b 2^-23 in [0, 1); R = sqrt(-2 ln U0), z0 = R cos(2 pi U1),
-// z1 = R sin(2 pi U1).  Both are read off one float: the bits 0x3F800000 | b
-// are X = 1 + b 2^-23 in [1, 2), so U0 = 2 - X (exact) and, since the gfx950
-// sine and cosine take their argument in revolutions and are periodic in it,
-// cos(2 pi U1) is the hardware cosine of X itself.  The hardware logarithm is
-// base 2, so ln U0 = ln 2 log2 U0.
+// (node, step, call j, stream id), j = 0..3.  The four words of a call carry
+// three Box-Muller pairs m = 0, 1, 2: the radius of pair m from the top 23
+// bits b = w_m >> 9 of word m, U0 = 1 - b 2^-23 in [2^-23, 1]; its angle from
+// 16 bits a no radius uses, U1 = a 2^-16 in [0, 1): a = w3 >> 16, w3 & 0xFFFF,
+// and (w0 & 0xFF) 2^8 + (w1 & 0xFF) for m = 0, 1, 2.  R = sqrt(-2 ln U0),
+// z0 = R cos(2 pi U1), z1 = R sin(2 pi U1).  Both uniforms are read off
+// floats in [1, 2): the bits 0x3F800000 | b are X = 1 + b 2^-23, so
+// U0 = 2 - X (exact), and the bits 0x3F800000 | a 2^7 are 1 + U1; since the
+// gfx950 sine and cosine take their argument in revolutions and are periodic
+// in it, cos(2 pi U1) is the hardware cosine of 1 + U1 itself.  The hardware
+// logarithm is base 2, so ln U0 = ln 2 log2 U0.
 #pragma once
 #include <cstdint>
 #include <hip/hip_runtime.h>
@@ -69,27 +71,43 @@ __device__ __forceinline__ float word_to_one_two(uint32_t w) {
   return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9));
 }
 
-// The radius uniform 1 - (w >> 9) 2^-23 in [2^-23, 1] and the angle uniform
-// (w >> 9) 2^-23 in [0, 1) of a word, exact in FP32.
+// The radius uniform 1 - (w >> 9) 2^-23 in [2^-23, 1] of a word, exact in FP32.
 __device__ __forceinline__ float radius_uniform(uint32_t w) { return 2.0f - word_to_one_two(w); }
-__device__ __forceinline__ float angle_uniform(uint32_t w) { return word_to_one_two(w) - 1.0f; }
+
+// 1 + a 2^-16 in [1, 2) for the 16 angle bits a of pair m of a call: the
+// 16-bit field placed at the top of the mantissa of a float of exponent 0.
+template <int M>
+__device__ __forceinline__ float angle_one_two(const Word4& w) {
+  uint32_t mant;
+  if constexpr (M == 0) mant = (w.w3 >> 9) & 0x7FFF80u;         // a = w3 >> 16
+  else if constexpr (M == 1) mant = (w.w3 << 7) & 0x7FFF80u;    // a = w3 & 0xFFFF
+  else mant = ((w.w0 & 0xFFu) << 15) | ((w.w1 & 0xFFu) << 7);   // a = (w0 & 0xFF) 2^8 + (w1 & 0xFF)
+  return __uint_as_float(0x3F800000u | mant);
+}
+
+// The angle uniform a 2^-16 in [0, 1) of pair m, exact in FP32.
+template <int M>
+__device__ __forceinline__ float angle_uniform(const Word4& w) { return angle_one_two<M>(w) - 1.0f; }
 
 constexpr float kMinus2Ln2 = -1.38629436111989061883f;  // -2 ln 2
 
-// Box-Muller pair from two words (radius word, angle word), both normals
-// multiplied by sqrt(c / (-2 ln 2)): the radius is sqrt(c log2 U0), so c = -2 ln 2
-// gives standard normals and c = -2 ln 2 rho gives sqrt(rho) times them.
-__device__ __forceinline__ void box_muller_scaled(uint32_t wr, uint32_t wa, float c, float& z0, float& z1) {
+// Box-Muller pair m of a call, both normals multiplied by sqrt(c / (-2 ln 2)):
+// the radius is sqrt(c log2 U0), so c = -2 ln 2 gives standard normals and
+// c = -2 ln 2 rho gives sqrt(rho) times them.
+template <int M>
+__device__ __forceinline__ void box_muller_scaled(const Word4& w, float c, float& z0, float& z1) {
+  const uint32_t wr = M == 0 ? w.w0 : (M == 1 ? w.w1 : w.w2);
   const float ur = radius_uniform(wr);
-  const float turns = word_to_one_two(wa);  // 1 + the angle uniform, in revolutions
+  const float turns = angle_one_two<M>(w);  // 1 + the angle uniform, in revolutions
   const float rad = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(ur));
   z0 = rad * __builtin_amdgcn_cosf(turns);
   z1 = rad * __builtin_amdgcn_sinf(turns);
 }
 
-// Standard normal Box-Muller pair.
-__device__ __forceinline__ void box_muller(uint32_t wr, uint32_t wa, float& z0, float& z1) {
-  box_muller_scaled(wr, wa, kMinus2Ln2, z0, z1);
+// Standard normal Box-Muller pair m of a call.
+template <int M>
+__device__ __forceinline__ void box_muller(const Word4& w, float& z0, float& z1) {
+  box_muller_scaled<M>(w, kMinus2Ln2, z0, z1);
 }
 
 }  // namespace rflbm
