@@ -7,7 +7,9 @@ index, step t), and compares population i of that post-collision state with
 what the GPU stored at y after the step, f_i(y, t + 1) = f*_i(y - c_i, t)
 (Eq. eq:streaming).  Two consecutive steps cover both AA parities.  Boxes:
 the 512^3 benchmark workload (FP32, FP16 and BF16 storage), a 1024^3 FP32 box
-(116 GB, 2^30 nodes), and two replicas of the 64-replica batch.
+(116 GB, 2^30 nodes), a 1024 x 2560 x 32 FP32 box whose row-block bricks must
+shrink to stay within 4 GiB per brick row, and two replicas of the 64-replica
+batch.
 """
 import numpy as np
 import pytest
@@ -131,6 +133,23 @@ def test_large_fp32_box_sampled(rf, ora):
     lat.init_equilibrium()
     p = ora.make_params(kT=1e-4, tau_shear=0.7, seed=5)
     pts = sample_nodes(dims, 96, seed=23)
+    for _ in range(2):
+        check_one_step(lat, ora, p, dims, pts)
+    lat.sync()
+    lat.close()
+
+
+def test_tall_fp32_box_smaller_bricks_sampled(rf, ora):
+    """A box whose brick rows of 16 planes (ny x 16 row blocks, 4.5 GB) would
+    pass the 4 GiB reach of the kernels' 32-bit lane offsets: the row blocks
+    then go in bricks of 8 planes (2.3 GB per brick row), and the sampled
+    parity holds on both AA parities (an offset past 4 GiB would not)."""
+    dims = (1024, 2560, 32)
+    print(f"[gpu] tall box {dims}", flush=True)
+    lat = rf.Lattice(dims, kT=1e-4, tau=0.8, seed=9)
+    lat.init_equilibrium()
+    p = ora.make_params(kT=1e-4, tau_shear=0.8, seed=9)
+    pts = sample_nodes(dims, 96, seed=29)
     for _ in range(2):
         check_one_step(lat, ora, p, dims, pts)
     lat.sync()
