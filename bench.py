@@ -459,7 +459,7 @@ def table3_protocol(dims=(256, 256, 256), reg_taus=(0.5001, 0.505, 0.51, 1.0, 10
 
 VALU_CMD = ("rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU -d <out>/prof_valu_{s} -o valu --output-format csv "
              "-- python3 bench.py --profile --profile-storage {s}")
-# Issue rate of plain FP32 vector instructions measured on the box (a probe of
+# Issue rate of plain FP32 vector instructions measured on the MI355X (a probe of
 # eight independent FMA chains per lane): 97.5 lanes per cycle per CU at the
 # 2.4 GHz peak clock, i.e. one wave64 instruction per 2.63 cycles per SIMD
 # (4 SIMDs per CU).  Transcendental instructions and 32 x 32 -> 64-bit
