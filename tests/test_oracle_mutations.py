@@ -4,8 +4,8 @@ Each case plants one mistake in a copy of the oracle's C source (on the CPU,
 in a scratch directory; the GPU path is not involved), rebuilds that copy and
 runs the oracle's pin tests against it: at least one pin must fail.  The
 mistakes are the kind a transcription of Table II, Eq. normal_fact,
-Eq. fluct_phi, Eq. r-flbe2, Eq. recursive_eq, Eq. eq:streaming or of the
-Philox round could contain.  The unmutated
+Eq. fluct_phi, Eq. r-flbe2, Eq. recursive_eq, Eq. eq:streaming, of the
+Philox round or of the layout of the uniforms in its words could contain.  The unmutated
 copy must pass, so a failure is the mistake's doing and not the harness's.
 """
 import os
@@ -43,6 +43,10 @@ MUTATIONS = [
     ("philox_key_increment", "#define PHILOX_WEYL_A 0x9E3779B9u", "#define PHILOX_WEYL_A 0x9E3779BBu"),
     ("philox_product_word", "uint32_t n1 = (uint32_t)pb;", "uint32_t n1 = (uint32_t)pa;"),
     ("philox_key_schedule", "    if (r > 0) {\n      k0 += PHILOX_WEYL_A;", "    if (r > 1) {\n      k0 += PHILOX_WEYL_A;"),
+    # the layout of the uniforms in the Philox words
+    ("angle_shares_radius_bits", "{w[3] >> 16, w[3] & 0xFFFFu,", "{w[0] >> 16, w[3] & 0xFFFFu,"),
+    ("radius_from_16_bits", "u[2 * m] = 1.0 - (double)(w[m] >> 9) / 8388608.0;",
+     "u[2 * m] = 1.0 - (double)(w[m] >> 16) / 65536.0;"),
 ]
 
 
