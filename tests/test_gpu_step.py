@@ -119,13 +119,14 @@ def test_trajectory_matches_oracle(rf, ora, case):
 
 @pytest.mark.parametrize("kT", [1e-4, 0.0])
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("dims", [(64, 3, 5), (128, 4, 3), (320, 2, 3), (1024, 3, 2)])
+@pytest.mark.parametrize("dims", [(64, 3, 5), (128, 4, 3), (320, 2, 3), (1024, 3, 2), (128, 4, 32)])
 def test_row_blocks_match_tiled_bitwise(rf, ora, dims, storage, kT):
     """The row-aligned steps (one-wave even steps, whole-row odd steps, whole-row
     statistics steps of both parities; used for FP32 and for k_BT = 0) store the
     same bits as the tiled ones, and their statistics agree with the tiled
     ones' to the rounding of their FP32 per-wave sums (the tiled steps add
-    every node in FP64)."""
+    every node in FP64).  The boxes take the plain layout and bricks of 2 x 1,
+    1 x 2 and 2 x 16 rows (the last with two bricks along y and two along z)."""
     print(f"[gpu] row blocks vs tiles {dims} {storage} kT={kT}", flush=True)
     f = initial_state(ora, dims, seed=21)
     extra = dict(storage_scale=1e-2) if (storage != "f32" and kT == 0.0) else {}
