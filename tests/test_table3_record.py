@@ -81,3 +81,21 @@ def test_spectra_reproduce_the_table(record):
             band = [v for k, (c, v) in enumerate(zip(counts, spec)) if 4 <= k <= 64 and c]
             lo, hi = r["fig2_min_max_k4_64"][g]
             assert lo == pytest.approx(min(band), abs=1.01e-4) and hi == pytest.approx(max(band), abs=1.01e-4)
+
+
+def test_shell_counts_are_the_wave_vectors_of_the_box(record):
+    """The GPU's structure-factor binning (a real-to-complex FFT, each stored
+    coefficient counted with its Hermitian partner) put every non-zero wave
+    vector n of the periodic 256^3 box in shell round(|n|): the counts it
+    recorded equal a direct count of the integer vectors, per shell."""
+    import numpy as np
+    nx, ny, nz = record["box"]
+    k = lambda n: np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n).astype(np.int64)
+    kxy2 = (k(nx)[:, None] ** 2 + k(ny)[None, :] ** 2).ravel()
+    counts = np.zeros(len(record["rows"][0]["shell_counts"]), dtype=np.int64)
+    for kz in k(nz):
+        shell = np.rint(np.sqrt(kxy2 + kz * kz)).astype(np.int64)
+        counts += np.bincount(shell, minlength=len(counts))[:len(counts)]
+    counts[0] -= 1  # n = 0 carries no fluctuation and is not binned
+    for r in record["rows"]:
+        assert r["shell_counts"] == counts.tolist(), (r["model"], r["tau"])
